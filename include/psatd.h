@@ -1,0 +1,155 @@
+/*
+ * psatd.h -- C ABI of the MI355X PSATD field step.
+ *
+ * The operation (Sec. III.B, item 2 of Blaclard, Vincenti, Lehe, Vay,
+ * arXiv:1608.05739; Table 1, PSATD row): on a periodic grid, forward-FFT the
+ * fields E, B and the sources J, rho; advance every k mode analytically over
+ * one time step with the sources held constant during the step (dispersion
+ * free, no Courant condition); inverse-FFT E and B.  The per-mode update, in
+ * normalized units with the forward transform f^(k) = sum_x f(x) e^{-i k.x}:
+ *
+ *   E^' = C E^ + i c^2 S (k x B^) - (S/eps0) J^ + i k (X3 rho^_old - X2 rho^_new)
+ *   B^' = C B^ - i S (k x E^) + i X1 (k x J^)
+ *
+ *   theta = c|k|dt,  C = cos theta,  S = sin theta / (c|k|),
+ *   X1 = (1 - C)/(eps0 c^2 |k|^2),  X2 = (1 - sin theta/theta)/(eps0 |k|^2),
+ *   X3 = (C - sin theta/theta)/(eps0 |k|^2)         (all finite at k = 0).
+ *
+ * (the "rho form"; the "J form" replaces the rho term by
+ *  eps0 c^2 X1 k (k.E^) - dt X2 k (k.J^), which assumes continuity.)
+ * The wavenumber of the Nyquist index of every (even) axis is taken as 0.
+ *
+ * Layout.  Every field component is a dense real array, x fastest:
+ * [nz][nx] in 2D (the (x, z) plane, ny = 1) and [nz][ny][nx] in 3D.  A plan
+ * may hold many independent patches; patch p occupies elements
+ * [offset_p, offset_p + nx*ny*nz) of every component buffer.  Element type is
+ * float (PSATD_FP32) or double (PSATD_FP64).  Buffers must be 8-byte aligned
+ * (FP32) or 16-byte aligned (FP64) at every patch offset.
+ *
+ * Ownership.  The caller owns all field buffers and the HIP stream.  A plan
+ * owns its device tables and, unless psatd_set_workspace was called, its
+ * workspace; psatd_destroy frees only plan-owned memory.
+ *
+ * Errors.  Every function returns a psatd_status.  Argument, size and state
+ * errors are detected on the host before anything is enqueued, so the fields
+ * are untouched; psatd_last_error() then describes the problem (thread-local
+ * text, valid until the next call on the same thread).  HIP launch errors give
+ * PSATD_ERR_HIP; faults inside kernels surface at the caller's next stream
+ * synchronization.  Nothing aborts or throws across this interface.
+ */
+#ifndef PSATD_H
+#define PSATD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psatd_plan_s* psatd_plan_t;
+
+typedef enum {
+  PSATD_OK = 0,
+  PSATD_ERR_INVALID_ARG = -1,      /* null pointer, bad enum, non-positive spacing or dt ... */
+  PSATD_ERR_UNSUPPORTED_SIZE = -2, /* axis length not an even 2^a 3^b in [2, 4096], ...      */
+  PSATD_ERR_OOM = -3,              /* device allocation failed                                */
+  PSATD_ERR_HIP = -4,              /* a HIP runtime call or kernel launch failed              */
+  PSATD_ERR_WORKSPACE = -5,        /* workspace missing, too small or misaligned              */
+  PSATD_ERR_STATE = -6             /* call not valid in the plan's current state              */
+} psatd_status;
+
+enum { PSATD_FP32 = 0, PSATD_FP64 = 1 };                               /* field element type */
+enum { PSATD_VACUUM = 0, PSATD_SOURCES_RHO = 1, PSATD_SOURCES_J = 2 }; /* update form        */
+enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel composition */
+
+/* psatd_config.flags */
+#define PSATD_FLAG_AUTOTUNE 0x1u /* time candidate launch shapes at plan time, keep the fastest */
+#define PSATD_FLAG_GRAPH 0x2u    /* replay a captured hipGraph of one step inside psatd_push   */
+#define PSATD_FLAG_NO_WORKSPACE 0x4u /* allocate no workspace: call psatd_set_workspace first */
+
+typedef struct {
+  int32_t ndim;  /* 2: (x, z) plane, n[1] must be 1;  3: (x, y, z)                   */
+  int32_t reserved0;
+  int64_t n[3];  /* nx, ny, nz: each an even 2^a 3^b with 2 <= n <= 4096 (ny = 1 in 2D) */
+  double d[3];   /* dx, dy, dz > 0 (dy ignored in 2D)                                 */
+  double dt;     /* > 0; no Courant limit                                             */
+  int64_t offset;/* element offset of this patch in every component buffer           */
+} psatd_patch_desc;
+
+typedef struct {
+  int32_t precision;   /* PSATD_FP32 or PSATD_FP64                                    */
+  int32_t source_mode; /* PSATD_VACUUM, PSATD_SOURCES_RHO or PSATD_SOURCES_J          */
+  int32_t path;        /* PSATD_PATH_FUSED or PSATD_PATH_PLAIN                        */
+  int32_t order;       /* 0: exact k; even p >= 2: order-p stencil wavevector k_p     */
+  double c;            /* speed of light (> 0; 1 in normalized units)                 */
+  double eps0;         /* vacuum permittivity (> 0; 1 in normalized units)           */
+  uint32_t flags;      /* PSATD_FLAG_*                                                */
+  int32_t reserved0;
+} psatd_config;
+
+typedef struct {
+  void* E[3];            /* in/out: Ex, Ey, Ez (device pointers, caller-owned)          */
+  void* B[3];            /* in/out: Bx, By, Bz                                           */
+  const void* J[3];      /* in: J^{n+1/2}; NULL for PSATD_VACUUM                         */
+  const void* rho_old;   /* in: rho^n (PSATD_SOURCES_RHO only, else NULL)                */
+  const void* rho_new;   /* in: rho^{n+1} (PSATD_SOURCES_RHO only, else NULL)            */
+} psatd_fields;
+
+/* Create a plan for npatches periodic patches on HIP device `device`.
+ * Validates every descriptor, builds the 1-D k tables, FFT twiddles and r2c
+ * post-twiddles in FP64 on the device, allocates the workspace (unless
+ * PSATD_FLAG_NO_WORKSPACE is set), optionally autotunes, and synchronizes
+ * once.  *out is set only on success. */
+psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches,
+                        int32_t npatches, int32_t device, psatd_plan_t* out);
+
+/* Bytes of device workspace the plan needs (the k-space spectra of all inputs). */
+psatd_status psatd_workspace_size(psatd_plan_t plan, size_t* bytes);
+
+/* Hand the plan a caller-owned device workspace of at least
+ * psatd_workspace_size() bytes, 256-byte aligned.  Frees any plan-owned
+ * workspace.  The caller keeps it alive until psatd_destroy. */
+psatd_status psatd_set_workspace(psatd_plan_t plan, void* device_ptr, size_t bytes);
+
+/* Advance the fields by nsteps steps, asynchronously on `hip_stream` (a
+ * hipStream_t; NULL = the default stream).  J is J^{n+1/2}, rho_old = rho^n,
+ * rho_new = rho^{n+1}; with sources nsteps must be 1.  No allocation, host
+ * synchronization or host copy happens here once the workspace exists, so the
+ * call can be captured into a hipGraph.  Not thread-safe for concurrent pushes
+ * on one plan. */
+psatd_status psatd_push(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
+                        void* hip_stream);
+
+/* Like psatd_push, but records a HIP event pair around every kernel launch on
+ * `hip_stream`, synchronizes at the end and writes the mean duration of each
+ * pass in milliseconds to ms_per_pass[0 .. npass-1] (npass from
+ * psatd_pass_count).  For measurement only. */
+psatd_status psatd_push_profiled(psatd_plan_t plan, const psatd_fields* fields,
+                                 int32_t nsteps, void* hip_stream, double* ms_per_pass,
+                                 int32_t max_pass);
+
+/* Number of kernel launches (passes) per step, and the name of pass i
+ * (static string, e.g. "x_r2c_fwd", "z_fused", "x_c2r_inv"). */
+psatd_status psatd_pass_count(psatd_plan_t plan, int32_t* npass);
+const char* psatd_pass_name(psatd_plan_t plan, int32_t i);
+
+/* Bytes each pass reads and writes in HBM per step by the pass model (fields,
+ * spectra; tables excluded).  Used to report achieved bandwidth. */
+psatd_status psatd_pass_bytes(psatd_plan_t plan, int32_t i, double* bytes);
+
+/* Human-readable description of the chosen kernels, tiles and launch shapes
+ * (NUL-terminated, truncated to len). */
+psatd_status psatd_plan_info(psatd_plan_t plan, char* buf, size_t len);
+
+/* Free plan-owned device memory and the plan.  NULL is accepted. */
+psatd_status psatd_destroy(psatd_plan_t plan);
+
+const char* psatd_status_string(psatd_status status);
+const char* psatd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSATD_H */

@@ -1,0 +1,16 @@
+"""MI355X-native PSATD field step (arXiv:1608.05739, Sec. III.B item 2).
+
+The compute path is the HIP library ``libpsatd.so`` (C ABI in
+``include/psatd.h``); this package is its Python binding.  There is no CPU
+fallback: if the library is not built, loading it raises.
+"""
+
+from ._binding import (  # noqa: F401
+    EXPORTED_SYMBOLS,
+    LIBRARY_PATH,
+    Patch,
+    Plan,
+    PsatdError,
+    as_patch,
+    load_library,
+)

@@ -1,0 +1,847 @@
+// Host side of the PSATD library: validation, planning, tables, launches and
+// the C ABI declared in include/psatd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "psatd.h"
+
+using namespace psatd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+psatd_status fail(psatd_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bool even_2a3b(int64_t n) {
+  if (n < 2 || n > 4096 || (n % 2) != 0) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// Radix schedule of a complex length L = 2^a 3^b (L = 1: no stages), largest
+// radices first, none above max_radix (16 or 8).
+std::vector<int> radix_plan(int L, int max_radix) {
+  int a = 0, b = 0;
+  while (L % 2 == 0) { L /= 2; ++a; }
+  while (L % 3 == 0) { L /= 3; ++b; }
+  std::vector<int> r;
+  const int big = max_radix >= 16 ? 4 : 3;
+  while (a >= big) { r.push_back(1 << big); a -= big; }
+  if (a == 3) r.push_back(8);
+  if (a == 2) r.push_back(4);
+  if (a == 1) r.push_back(2);
+  for (int i = 0; i < b; ++i) r.push_back(3);
+  return r;
+}
+
+bool has_radix3(int L) { return L % 3 == 0; }
+
+// Points a thread may own in a stage when at most maxpts fit its registers:
+// radix-3 stages hold 3 * floor(maxpts / 3).
+int points_per_thread(int L, int maxpts) { return has_radix3(L) ? 3 * (maxpts / 3) : maxpts; }
+
+// Threads needed so that no thread holds more than kMaxPts points in a stage.
+int threads_for(int points, int L) {
+  const int per = points_per_thread(L, kMaxPts);
+  int t = (points + per - 1) / per;
+  t = ((t + 63) / 64) * 64;
+  return std::max(64, t);
+}
+
+// Staggered-grid Fornberg weights C_1..C_{p/2}: C_l = L_l(0) / x_l for the
+// Lagrange basis on nodes +-1/2, ..., +-(p-1)/2 (derivative at 0).
+std::vector<double> fornberg_staggered(int p) {
+  std::vector<double> nodes;
+  for (int j = 0; j < p; ++j) nodes.push_back((2.0 * j - p + 1) / 2.0);
+  std::vector<double> w;
+  for (int l = 1; l <= p / 2; ++l) {
+    const double xj = (2.0 * l - 1) / 2.0;
+    double L0 = 1.0;
+    for (double xn : nodes)
+      if (xn != xj) L0 *= (0.0 - xn) / (xj - xn);
+    w.push_back(L0 / xj);
+  }
+  return w;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+enum PassType { kLine = 0, kFused = 1, kUpdate = 2 };
+
+struct Pass {
+  PassType type;
+  int line_kind;
+  const char* name;
+  LaunchShape shape;
+  WorkItem* d_items = nullptr;
+  int nitems = 0;
+  double bytes = 0.0;
+  int mpt = 0;
+};
+
+const char* line_pass_name(int kind) {
+  switch (kind) {
+    case kXFwd: return "x_r2c_fwd";
+    case kXInv: return "x_c2r_inv";
+    case kYFwd: return "y_c2c_fwd";
+    case kYInv: return "y_c2c_inv";
+    case kZFwd: return "z_c2c_fwd";
+    default: return "z_c2c_inv";
+  }
+}
+
+}  // namespace
+
+struct psatd_plan_s {
+  psatd_config cfg{};
+  int device = 0;
+  int ndim = 2;
+  int nin = 6;      // input components
+  size_t elem = 4;  // sizeof storage scalar
+  std::vector<psatd_patch_desc> desc;
+  std::vector<PatchDev> host_patches;
+  PatchDev* d_patches = nullptr;
+  void* d_tables = nullptr;
+  void* d_items = nullptr;
+  void* ws = nullptr;
+  bool ws_owned = false;
+  size_t ws_bytes = 0;
+  std::vector<Pass> passes;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  FieldPtrs graph_fields{};
+  hipStream_t graph_stream = nullptr;
+  std::string info;
+};
+
+namespace {
+
+void free_plan_memory(psatd_plan_s* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->d_patches) (void)hipFree(p->d_patches);
+  if (p->d_tables) (void)hipFree(p->d_tables);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->ws && p->ws_owned) (void)hipFree(p->ws);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  p->capture_stream = nullptr;
+  p->d_patches = nullptr;
+  p->d_tables = nullptr;
+  p->d_items = nullptr;
+  p->ws = nullptr;
+}
+
+psatd_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? PSATD_ERR_OOM : PSATD_ERR_HIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t np) {
+  if (!cfg) return fail(PSATD_ERR_INVALID_ARG, "cfg is NULL");
+  if (!patches) return fail(PSATD_ERR_INVALID_ARG, "patches is NULL");
+  if (np < 1) return fail(PSATD_ERR_INVALID_ARG, "npatches must be >= 1");
+  if (cfg->precision != PSATD_FP32 && cfg->precision != PSATD_FP64)
+    return fail(PSATD_ERR_INVALID_ARG, "precision must be PSATD_FP32 or PSATD_FP64");
+  if (cfg->source_mode < PSATD_VACUUM || cfg->source_mode > PSATD_SOURCES_J)
+    return fail(PSATD_ERR_INVALID_ARG, "unknown source_mode");
+  if (cfg->path != PSATD_PATH_FUSED && cfg->path != PSATD_PATH_PLAIN)
+    return fail(PSATD_ERR_INVALID_ARG, "unknown path");
+  if (cfg->order < 0 || cfg->order % 2 != 0 || cfg->order > 512)
+    return fail(PSATD_ERR_INVALID_ARG, "order must be 0 or an even number in [2, 512]");
+  if (!(cfg->c > 0.0) || !std::isfinite(cfg->c)) return fail(PSATD_ERR_INVALID_ARG, "c must be > 0");
+  if (!(cfg->eps0 > 0.0) || !std::isfinite(cfg->eps0))
+    return fail(PSATD_ERR_INVALID_ARG, "eps0 must be > 0");
+  if (cfg->flags & ~(PSATD_FLAG_AUTOTUNE | PSATD_FLAG_GRAPH | PSATD_FLAG_NO_WORKSPACE))
+    return fail(PSATD_ERR_INVALID_ARG, "unknown flag bits");
+  const int ndim = patches[0].ndim;
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  for (int i = 0; i < np; ++i) {
+    const psatd_patch_desc& d = patches[i];
+    const std::string tag = "patch " + std::to_string(i) + ": ";
+    if (d.ndim != 2 && d.ndim != 3) return fail(PSATD_ERR_INVALID_ARG, tag + "ndim must be 2 or 3");
+    if (d.ndim != ndim)
+      return fail(PSATD_ERR_INVALID_ARG, tag + "all patches of a plan must have the same ndim");
+    if (d.ndim == 2 && d.n[1] != 1) return fail(PSATD_ERR_INVALID_ARG, tag + "2D patches need n[1] = 1");
+    for (int a = 0; a < 3; ++a) {
+      if (d.ndim == 2 && a == 1) continue;
+      if (!even_2a3b(d.n[a]))
+        return fail(PSATD_ERR_UNSUPPORTED_SIZE,
+                    tag + "axis " + std::to_string(a) + " length " + std::to_string(d.n[a]) +
+                        " is not an even 2^a 3^b in [2, 4096]");
+      if (!(d.d[a] > 0.0) || !std::isfinite(d.d[a]))
+        return fail(PSATD_ERR_INVALID_ARG, tag + "grid spacing must be > 0");
+    }
+    if (!(d.dt > 0.0) || !std::isfinite(d.dt)) return fail(PSATD_ERR_INVALID_ARG, tag + "dt must be > 0");
+    if (d.offset < 0 || (d.offset % 2) != 0)
+      return fail(PSATD_ERR_INVALID_ARG, tag + "offset must be a non-negative even element index");
+    const int64_t cells = d.n[0] * (d.ndim == 3 ? d.n[1] : 1) * d.n[2];
+    if (cells > (int64_t(1) << 31))
+      return fail(PSATD_ERR_UNSUPPORTED_SIZE, tag + "more than 2^31 cells in one patch");
+    ranges.emplace_back(d.offset, d.offset + cells);
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second)
+      return fail(PSATD_ERR_INVALID_ARG, "patches overlap in the component buffers");
+  return PSATD_OK;
+}
+
+int inputs_for(int src) { return src == PSATD_VACUUM ? 6 : (src == PSATD_SOURCES_J ? 9 : 11); }
+
+// Lines of a line pass for one patch and its FFT length.
+void line_geometry(int kind, const PatchDev& P, int* nlines, int* L) {
+  switch (kind) {
+    case kXFwd:
+    case kXInv:
+      *nlines = P.nz * P.ny;
+      *L = P.mx;
+      break;
+    case kYFwd:
+    case kYInv:
+      *nlines = P.mx * P.nz;
+      *L = P.ny;
+      break;
+    default:
+      *nlines = P.mx * P.ny;
+      *L = P.nz;
+      break;
+  }
+}
+
+// Build a line pass over all patches for the given components.
+Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
+                    std::vector<WorkItem>& items, int lines_override = 0) {
+  Pass ps;
+  ps.type = kLine;
+  ps.line_kind = kind;
+  ps.name = line_pass_name(kind);
+  const bool transposing = kind == kXFwd || kind == kXInv || kind == kYFwd || kind == kYInv;
+  const int want = lines_override > 0 ? lines_override : (plan->elem == 4 ? 8 : 4);
+  int block = 64;
+  size_t lds = 0;
+  const size_t first = items.size();
+  double bytes = 0.0;
+  for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+    const PatchDev& P = plan->host_patches[pi];
+    int nlines, L;
+    line_geometry(kind, P, &nlines, &L);
+    int R;
+    if (transposing) {
+      R = want;
+    } else {
+      R = std::max(1, 4096 / L);
+    }
+    R = std::min(R, nlines);
+    // LDS holds R lines (<= 128 KB) and 512 threads own every stage's points
+    const int max_pts = std::min(8192, kLineBlockMax * points_per_thread(L, kMaxPts));
+    R = std::max(1, std::min(R, max_pts / L));
+    block = std::max(block, threads_for(R * L, L));
+    lds = std::max(lds, static_cast<size_t>(R) * L * sizeof(double2));
+    for (int c : comps)
+      for (int l = 0; l < nlines; l += R)
+        items.push_back(WorkItem{static_cast<int>(pi), l, std::min(R, nlines - l), c});
+    const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+    bytes += comps.size() * 2.0 * cells * plan->elem;
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  ps.shape = LaunchShape{ps.nitems, std::min(block, kLineBlockMax), lds};
+  ps.bytes = bytes;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);  // offset, fixed up after upload
+  return ps;
+}
+
+int fused_mpt(int precision, int ndim) {
+  if (precision == PSATD_FP32) return ndim == 2 ? 8 : 4;
+  return ndim == 2 ? 4 : 2;
+}
+
+psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out) {
+  Pass ps;
+  ps.type = kFused;
+  ps.name = "z_fused";
+  ps.mpt = fused_mpt(plan->cfg.precision, plan->ndim);
+  const int block = kFusedBlock;
+  const int modes = block * ps.mpt;
+  const size_t first = items.size();
+  size_t lds = 0;
+  double bytes = 0.0;
+  for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+    const PatchDev& P = plan->host_patches[pi];
+    const int nlines = P.mx * P.ny;
+    if (P.nz > modes)
+      return fail(PSATD_ERR_UNSUPPORTED_SIZE,
+                  "fused path: nz = " + std::to_string(P.nz) + " exceeds " + std::to_string(modes) +
+                      " modes per workgroup at this precision; use PSATD_PATH_PLAIN");
+    // lines per workgroup: all modes must fit T * MPT, and every FFT stage must
+    // leave at most kMaxPtsFused points per thread
+    const int cap = std::min(modes, block * points_per_thread(P.nz, kMaxPtsFused));
+    if (P.nz > cap)
+      return fail(PSATD_ERR_UNSUPPORTED_SIZE,
+                  "fused path: nz = " + std::to_string(P.nz) + " does not fit one workgroup");
+    const int W = std::max(1, std::min(nlines, cap / P.nz));
+    lds = std::max(lds, static_cast<size_t>(W) * P.nz * sizeof(double2));
+    for (int l = 0; l < nlines; l += W)
+      items.push_back(WorkItem{static_cast<int>(pi), l, std::min(W, nlines - l), -1});
+    const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+    bytes += (plan->nin + 6) * cells * plan->elem;
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  ps.shape = LaunchShape{ps.nitems, block, lds};
+  ps.bytes = bytes;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);
+  *out = ps;
+  return PSATD_OK;
+}
+
+Pass make_update_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
+  Pass ps;
+  ps.type = kUpdate;
+  ps.name = "update";
+  const size_t first = items.size();
+  const int chunk = 4096;
+  double bytes = 0.0;
+  for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+    const PatchDev& P = plan->host_patches[pi];
+    const long long modes = P.comp_stride;
+    for (long long m = 0; m < modes; m += chunk)
+      items.push_back(WorkItem{static_cast<int>(pi), static_cast<int>(m),
+                               static_cast<int>(std::min<long long>(chunk, modes - m)), -1});
+    const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+    bytes += (plan->nin + 6) * cells * plan->elem;
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  ps.shape = LaunchShape{ps.nitems, 256, 0};
+  ps.bytes = bytes;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);
+  return ps;
+}
+
+// Host check of the invariants every kernel relies on, run once per plan
+// before anything can be launched: work items stay inside their patch, LDS
+// holds every item, and in each FFT stage the block owns all butterflies
+// within the per-thread register budget.
+psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkItem* items) {
+  const int maxpts = ps.type == kFused ? kMaxPtsFused : kMaxPts;
+  for (int i = 0; i < ps.nitems; ++i) {
+    const WorkItem& w = items[i];
+    if (w.patch < 0 || w.patch >= static_cast<int>(plan->host_patches.size()))
+      return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad patch index");
+    const PatchDev& P = plan->host_patches[w.patch];
+    if (w.count < 1 || w.first < 0) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": empty item");
+    if (ps.type == kUpdate) {
+      if (static_cast<long long>(w.first) + w.count > P.comp_stride)
+        return fail(PSATD_ERR_STATE, "update: item past the spectrum");
+      continue;
+    }
+    int nlines, L;
+    const FFTPlanDev* f;
+    if (ps.type == kFused) {
+      nlines = P.mx * P.ny;
+      L = P.nz;
+      f = &P.fz;
+    } else {
+      line_geometry(ps.line_kind, P, &nlines, &L);
+      f = (ps.line_kind == kXFwd || ps.line_kind == kXInv)   ? &P.fx
+          : (ps.line_kind == kYFwd || ps.line_kind == kYInv) ? &P.fy
+                                                             : &P.fz;
+      if (w.comp < 0 || w.comp >= plan->nin)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad component");
+    }
+    if (w.first + w.count > nlines)
+      return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item past the last line");
+    const long long pts = static_cast<long long>(w.count) * L;
+    if (pts * static_cast<long long>(sizeof(double2)) > static_cast<long long>(ps.shape.lds_bytes))
+      return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item exceeds LDS");
+    if (ps.type == kFused && pts > static_cast<long long>(ps.shape.block) * ps.mpt)
+      return fail(PSATD_ERR_STATE, "z_fused: modes exceed registers");
+    for (int s = 0; s < f->nstages; ++s) {
+      const int r = f->radix[s];
+      if (r > maxpts) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": radix too large");
+      const long long bpt = maxpts / r;
+      if (pts / r > bpt * ps.shape.block)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": too few threads for a stage");
+    }
+  }
+  if (ps.shape.lds_bytes > 160 * 1024) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": LDS > 160 KB");
+  if (ps.shape.block < 64 || ps.shape.block > 1024)
+    return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad block size");
+  return PSATD_OK;
+}
+
+psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldPtrs& f,
+                          hipStream_t s) {
+  hipError_t e;
+  const Physics ph{plan->cfg.c, plan->cfg.eps0};
+  switch (ps.type) {
+    case kLine:
+      e = launch_line_pass(ps.line_kind, plan->cfg.precision, ps.shape, s, plan->d_patches,
+                           ps.d_items, ps.nitems, f, plan->ws);
+      break;
+    case kFused:
+      e = launch_fused_z(plan->cfg.precision, plan->ndim, plan->cfg.source_mode, ps.mpt, ps.shape,
+                         s, plan->d_patches, ps.d_items, ps.nitems, plan->ws, ph);
+      break;
+    default:
+      e = launch_update(plan->cfg.precision, plan->cfg.source_mode, ps.shape, s, plan->d_patches,
+                        ps.d_items, ps.nitems, plan->ws, ph);
+      break;
+  }
+  if (e != hipSuccess) return hip_fail(e, ps.name);
+  return PSATD_OK;
+}
+
+psatd_status check_fields(const psatd_plan_s* plan, const psatd_fields* f, FieldPtrs* out) {
+  if (!f) return fail(PSATD_ERR_INVALID_ARG, "fields is NULL");
+  for (int i = 0; i < 3; ++i) {
+    if (!f->E[i] || !f->B[i]) return fail(PSATD_ERR_INVALID_ARG, "E and B pointers must be non-NULL");
+  }
+  const int src = plan->cfg.source_mode;
+  if (src != PSATD_VACUUM) {
+    for (int i = 0; i < 3; ++i)
+      if (!f->J[i]) return fail(PSATD_ERR_INVALID_ARG, "J pointers must be non-NULL with sources");
+  }
+  if (src == PSATD_SOURCES_RHO && (!f->rho_old || !f->rho_new))
+    return fail(PSATD_ERR_INVALID_ARG, "rho_old and rho_new must be non-NULL in the rho form");
+  const size_t align = plan->elem * 2;
+  auto misaligned = [&](const void* p) { return (reinterpret_cast<uintptr_t>(p) % align) != 0; };
+  FieldPtrs fp{};
+  for (int i = 0; i < 3; ++i) {
+    fp.f[kEx + i] = f->E[i];
+    fp.f[kBx + i] = f->B[i];
+    fp.f[kJx + i] = const_cast<void*>(f->J[i]);
+  }
+  fp.f[kRhoOld] = const_cast<void*>(f->rho_old);
+  fp.f[kRhoNew] = const_cast<void*>(f->rho_new);
+  for (int i = 0; i < plan->nin; ++i)
+    if (misaligned(fp.f[i]))
+      return fail(PSATD_ERR_INVALID_ARG, "field buffers must be aligned to two elements");
+  *out = fp;
+  return PSATD_OK;
+}
+
+psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStream_t s) {
+  for (const Pass& ps : plan->passes) {
+    psatd_status st = enqueue_pass(plan, ps, fp, s);
+    if (st != PSATD_OK) return st;
+  }
+  return PSATD_OK;
+}
+
+bool same_fields(const FieldPtrs& a, const FieldPtrs& b) {
+  return std::memcmp(&a, &b, sizeof(FieldPtrs)) == 0;
+}
+
+psatd_status build_plan(psatd_plan_s* plan) {
+  const psatd_config& cfg = plan->cfg;
+  plan->ndim = plan->desc[0].ndim;
+  plan->nin = inputs_for(cfg.source_mode);
+  plan->elem = cfg.precision == PSATD_FP32 ? 4 : 8;
+
+  // ---- tables layout (bytes): per patch kx, ky, kz, post; per FFT length twiddles
+  std::map<int, size_t> tw_off;
+  size_t tb = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = tb;
+    tb += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  struct PT { size_t kx, ky, kz, post; };
+  std::vector<PT> pt;
+  for (const psatd_patch_desc& d : plan->desc) {
+    const int nx = static_cast<int>(d.n[0]);
+    const int ny = plan->ndim == 3 ? static_cast<int>(d.n[1]) : 1;
+    const int nz = static_cast<int>(d.n[2]);
+    const int mx = nx / 2;
+    PT t;
+    t.kx = take(sizeof(double) * mx);
+    t.ky = take(sizeof(double) * ny);
+    t.kz = take(sizeof(double) * nz);
+    t.post = take(sizeof(double2) * mx);
+    pt.push_back(t);
+    for (int L : {mx, ny, nz})
+      if (!tw_off.count(L)) tw_off[L] = take(sizeof(double2) * L);
+  }
+  std::vector<double> fw;
+  if (cfg.order > 0) fw = fornberg_staggered(cfg.order);
+  const size_t fw_off = take(sizeof(double) * std::max<size_t>(1, fw.size()));
+
+  hipError_t e = hipMalloc(&plan->d_tables, tb);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
+  char* T = static_cast<char*>(plan->d_tables);
+  if (!fw.empty()) {
+    e = hipMemcpy(T + fw_off, fw.data(), sizeof(double) * fw.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fornberg)");
+  }
+  const double* d_fw = reinterpret_cast<const double*>(T + fw_off);
+  const int nfw = static_cast<int>(fw.size());
+
+  for (auto& kv : tw_off) {
+    e = launch_twiddles(reinterpret_cast<double2*>(T + kv.second), kv.first, kv.first, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "twiddle table");
+  }
+
+  // ---- patch descriptors and workspace layout
+  long long spec_off = 0;
+  plan->host_patches.clear();
+  for (size_t i = 0; i < plan->desc.size(); ++i) {
+    const psatd_patch_desc& d = plan->desc[i];
+    PatchDev P{};
+    P.ndim = plan->ndim;
+    P.nx = static_cast<int>(d.n[0]);
+    P.ny = plan->ndim == 3 ? static_cast<int>(d.n[1]) : 1;
+    P.nz = static_cast<int>(d.n[2]);
+    P.mx = P.nx / 2;
+    P.dt = d.dt;
+    P.inv_n = 1.0 / (static_cast<double>(P.nx) * P.ny * P.nz);
+    P.off_real = d.offset;
+    P.comp_stride = static_cast<long long>(P.mx) * P.ny * P.nz;
+    P.off_spec = spec_off;
+    spec_off += (P.comp_stride * plan->nin + 63) / 64 * 64;
+    P.kx = reinterpret_cast<const double*>(T + pt[i].kx);
+    P.ky = reinterpret_cast<const double*>(T + pt[i].ky);
+    P.kz = reinterpret_cast<const double*>(T + pt[i].kz);
+    P.post = reinterpret_cast<const double2*>(T + pt[i].post);
+    auto fill = [&](FFTPlanDev& f, int L, int max_radix) {
+      const std::vector<int> r = radix_plan(L, max_radix);
+      f.n = L;
+      f.nstages = static_cast<int>(r.size());
+      for (size_t s = 0; s < r.size(); ++s) f.radix[s] = r[s];
+      f.tw = reinterpret_cast<const double2*>(T + tw_off[L]);
+    };
+    fill(P.fx, P.mx, 16);
+    fill(P.fy, P.ny, 16);
+    fill(P.fz, P.nz, kMaxRadixZ);
+    plan->host_patches.push_back(P);
+
+    e = launch_ktable(const_cast<double*>(P.kx), P.nx, d.d[0], P.mx, 1, d_fw, nfw, nullptr);
+    if (e == hipSuccess && plan->ndim == 3)
+      e = launch_ktable(const_cast<double*>(P.ky), P.ny, d.d[1], P.ny, 0, d_fw, nfw, nullptr);
+    if (e == hipSuccess && plan->ndim == 2) {
+      const double zero = 0.0;
+      e = hipMemcpy(const_cast<double*>(P.ky), &zero, sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+      e = launch_ktable(const_cast<double*>(P.kz), P.nz, d.d[2], P.nz, 0, d_fw, nfw, nullptr);
+    if (e == hipSuccess)
+      e = launch_twiddles(const_cast<double2*>(P.post), P.nx, P.mx, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "k tables");
+  }
+  plan->ws_bytes = static_cast<size_t>(spec_off) * 2 * plan->elem;
+
+  e = hipMalloc(&plan->d_patches, sizeof(PatchDev) * plan->host_patches.size());
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(patches)");
+  e = hipMemcpy(plan->d_patches, plan->host_patches.data(),
+                sizeof(PatchDev) * plan->host_patches.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(patches)");
+
+  // ---- passes
+  std::vector<int> in_comps, out_comps;
+  for (int c = 0; c < plan->nin; ++c) in_comps.push_back(c);
+  for (int c = 0; c < 6; ++c) out_comps.push_back(c);
+  std::vector<WorkItem> items;
+  plan->passes.clear();
+  plan->passes.push_back(make_line_pass(kXFwd, plan, in_comps, items));
+  if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYFwd, plan, in_comps, items));
+  if (cfg.path == PSATD_PATH_FUSED) {
+    Pass fz;
+    psatd_status st = make_fused_pass(plan, items, &fz);
+    if (st != PSATD_OK) return st;
+    plan->passes.push_back(fz);
+  } else {
+    plan->passes.push_back(make_line_pass(kZFwd, plan, in_comps, items));
+    plan->passes.push_back(make_update_pass(plan, items));
+    plan->passes.push_back(make_line_pass(kZInv, plan, out_comps, items));
+  }
+  if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYInv, plan, out_comps, items));
+  plan->passes.push_back(make_line_pass(kXInv, plan, out_comps, items));
+
+  for (const Pass& ps : plan->passes) {
+    psatd_status st = verify_pass(plan, ps, items.data() + reinterpret_cast<size_t>(ps.d_items));
+    if (st != PSATD_OK) return st;
+  }
+  e = hipMalloc(&plan->d_items, sizeof(WorkItem) * items.size());
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(work items)");
+  e = hipMemcpy(plan->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work items)");
+  for (Pass& ps : plan->passes)
+    ps.d_items = static_cast<WorkItem*>(plan->d_items) + reinterpret_cast<size_t>(ps.d_items);
+
+  if (!(cfg.flags & PSATD_FLAG_NO_WORKSPACE)) {
+    e = hipMalloc(&plan->ws, plan->ws_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    plan->ws_owned = true;
+  }
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "plan tables");
+
+  char buf[512];
+  plan->info.clear();
+  std::snprintf(buf, sizeof(buf), "ndim=%d patches=%zu precision=%s source=%d path=%s order=%d ws=%zu\n",
+                plan->ndim, plan->host_patches.size(), cfg.precision == PSATD_FP32 ? "fp32" : "fp64",
+                cfg.source_mode, cfg.path == PSATD_PATH_FUSED ? "fused" : "plain", cfg.order,
+                plan->ws_bytes);
+  plan->info += buf;
+  for (const Pass& ps : plan->passes) {
+    std::snprintf(buf, sizeof(buf), "  %-10s items=%d block=%d lds=%zu mpt=%d bytes=%.0f\n",
+                  ps.name, ps.nitems, ps.shape.block, ps.shape.lds_bytes, ps.mpt, ps.bytes);
+    plan->info += buf;
+  }
+  return PSATD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t npatches,
+                        int32_t device, psatd_plan_t* out) {
+  try {
+    if (!out) return fail(PSATD_ERR_INVALID_ARG, "out is NULL");
+    psatd_status st = validate(cfg, patches, npatches);
+    if (st != PSATD_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+      return fail(PSATD_ERR_HIP, "no HIP device available");
+    if (device < 0 || device >= ndev)
+      return fail(PSATD_ERR_INVALID_ARG, "device index out of range");
+    DeviceGuard g(device);
+    if (!g.ok) return fail(PSATD_ERR_HIP, "hipSetDevice failed");
+    static bool attrs = false;
+    if (!attrs) {
+      hipError_t e = configure_kernel_attributes();
+      if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+      attrs = true;
+    }
+    psatd_plan_s* plan = new psatd_plan_s();
+    plan->cfg = *cfg;
+    plan->device = device;
+    plan->desc.assign(patches, patches + npatches);
+    st = build_plan(plan);
+    if (st != PSATD_OK) {
+      free_plan_memory(plan);
+      delete plan;
+      return st;
+    }
+    *out = plan;
+    return PSATD_OK;
+  } catch (const std::exception& ex) {
+    return fail(PSATD_ERR_OOM, std::string("host allocation failed: ") + ex.what());
+  } catch (...) {
+    return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+psatd_status psatd_workspace_size(psatd_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(PSATD_ERR_INVALID_ARG, "NULL argument");
+  *bytes = plan->ws_bytes;
+  return PSATD_OK;
+}
+
+psatd_status psatd_set_workspace(psatd_plan_t plan, void* ptr, size_t bytes) {
+  if (!plan || !ptr) return fail(PSATD_ERR_INVALID_ARG, "NULL argument");
+  if (bytes < plan->ws_bytes)
+    return fail(PSATD_ERR_WORKSPACE, "workspace of " + std::to_string(bytes) + " bytes < required " +
+                                         std::to_string(plan->ws_bytes));
+  if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+    return fail(PSATD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  DeviceGuard g(plan->device);
+  if (plan->ws && plan->ws_owned) (void)hipFree(plan->ws);
+  plan->ws = ptr;
+  plan->ws_owned = false;
+  if (plan->graph_exec) {
+    (void)hipGraphExecDestroy(plan->graph_exec);
+    (void)hipGraphDestroy(plan->graph);
+    plan->graph_exec = nullptr;
+    plan->graph = nullptr;
+  }
+  return PSATD_OK;
+}
+
+static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
+                              void* hip_stream, double* ms_per_pass, int32_t max_pass) {
+  if (!plan) return fail(PSATD_ERR_INVALID_ARG, "plan is NULL");
+  if (nsteps < 0) return fail(PSATD_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (nsteps > 1 && plan->cfg.source_mode != PSATD_VACUUM)
+    return fail(PSATD_ERR_INVALID_ARG, "with sources, push one step at a time (nsteps = 1)");
+  if (!plan->ws) return fail(PSATD_ERR_WORKSPACE, "no workspace: call psatd_set_workspace");
+  FieldPtrs fp;
+  psatd_status st = check_fields(plan, fields, &fp);
+  if (st != PSATD_OK) return st;
+  if (nsteps == 0) return PSATD_OK;
+  DeviceGuard g(plan->device);
+  if (!g.ok) return fail(PSATD_ERR_HIP, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+
+  if (ms_per_pass) {
+    const int np = static_cast<int>(plan->passes.size());
+    if (max_pass < np) return fail(PSATD_ERR_INVALID_ARG, "ms_per_pass holds fewer than npass entries");
+    std::vector<hipEvent_t> ev(2 * np * nsteps);
+    for (auto& x : ev)
+      if (hipEventCreate(&x) != hipSuccess) return fail(PSATD_ERR_HIP, "hipEventCreate");
+    psatd_status rs = PSATD_OK;
+    for (int n = 0; n < nsteps && rs == PSATD_OK; ++n)
+      for (int i = 0; i < np && rs == PSATD_OK; ++i) {
+        (void)hipEventRecord(ev[2 * (n * np + i)], s);
+        rs = enqueue_pass(plan, plan->passes[i], fp, s);
+        (void)hipEventRecord(ev[2 * (n * np + i) + 1], s);
+      }
+    hipError_t e = hipStreamSynchronize(s);
+    for (int i = 0; i < np; ++i) ms_per_pass[i] = 0.0;
+    if (rs == PSATD_OK && e == hipSuccess) {
+      for (int n = 0; n < nsteps; ++n)
+        for (int i = 0; i < np; ++i) {
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, ev[2 * (n * np + i)], ev[2 * (n * np + i) + 1]);
+          ms_per_pass[i] += ms / nsteps;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (rs != PSATD_OK) return rs;
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    return PSATD_OK;
+  }
+
+  if (plan->cfg.flags & PSATD_FLAG_GRAPH) {
+    if (!plan->graph_exec || !same_fields(plan->graph_fields, fp)) {
+      if (plan->graph_exec) {
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph_exec = nullptr;
+        plan->graph = nullptr;
+      }
+      if (!plan->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+      }
+      hipError_t e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      psatd_status cs = enqueue_step(plan, fp, plan->capture_stream);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(plan->capture_stream, &graph);
+      if (cs != PSATD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cs;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      plan->graph = graph;
+      plan->graph_fields = fp;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+      hipError_t e = hipGraphLaunch(plan->graph_exec, s);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    return PSATD_OK;
+  }
+
+  for (int n = 0; n < nsteps; ++n) {
+    st = enqueue_step(plan, fp, s);
+    if (st != PSATD_OK) return st;
+  }
+  return PSATD_OK;
+}
+
+psatd_status psatd_push(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
+                        void* hip_stream) {
+  try {
+    return push_impl(plan, fields, nsteps, hip_stream, nullptr, 0);
+  } catch (...) {
+    return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+psatd_status psatd_push_profiled(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
+                                 void* hip_stream, double* ms_per_pass, int32_t max_pass) {
+  if (!ms_per_pass) return fail(PSATD_ERR_INVALID_ARG, "ms_per_pass is NULL");
+  if (nsteps < 1) return fail(PSATD_ERR_INVALID_ARG, "nsteps must be >= 1");
+  try {
+    return push_impl(plan, fields, nsteps, hip_stream, ms_per_pass, max_pass);
+  } catch (...) {
+    return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+psatd_status psatd_pass_count(psatd_plan_t plan, int32_t* npass) {
+  if (!plan || !npass) return fail(PSATD_ERR_INVALID_ARG, "NULL argument");
+  *npass = static_cast<int32_t>(plan->passes.size());
+  return PSATD_OK;
+}
+
+const char* psatd_pass_name(psatd_plan_t plan, int32_t i) {
+  if (!plan || i < 0 || i >= static_cast<int32_t>(plan->passes.size())) return nullptr;
+  return plan->passes[i].name;
+}
+
+psatd_status psatd_pass_bytes(psatd_plan_t plan, int32_t i, double* bytes) {
+  if (!plan || !bytes) return fail(PSATD_ERR_INVALID_ARG, "NULL argument");
+  if (i < 0 || i >= static_cast<int32_t>(plan->passes.size()))
+    return fail(PSATD_ERR_INVALID_ARG, "pass index out of range");
+  *bytes = plan->passes[i].bytes;
+  return PSATD_OK;
+}
+
+psatd_status psatd_plan_info(psatd_plan_t plan, char* buf, size_t len) {
+  if (!plan || !buf || len == 0) return fail(PSATD_ERR_INVALID_ARG, "NULL argument");
+  std::snprintf(buf, len, "%s", plan->info.c_str());
+  return PSATD_OK;
+}
+
+psatd_status psatd_destroy(psatd_plan_t plan) {
+  if (!plan) return PSATD_OK;
+  {
+    DeviceGuard g(plan->device);
+    free_plan_memory(plan);
+  }
+  delete plan;
+  return PSATD_OK;
+}
+
+const char* psatd_status_string(psatd_status s) {
+  switch (s) {
+    case PSATD_OK: return "PSATD_OK";
+    case PSATD_ERR_INVALID_ARG: return "PSATD_ERR_INVALID_ARG";
+    case PSATD_ERR_UNSUPPORTED_SIZE: return "PSATD_ERR_UNSUPPORTED_SIZE";
+    case PSATD_ERR_OOM: return "PSATD_ERR_OOM";
+    case PSATD_ERR_HIP: return "PSATD_ERR_HIP";
+    case PSATD_ERR_WORKSPACE: return "PSATD_ERR_WORKSPACE";
+    case PSATD_ERR_STATE: return "PSATD_ERR_STATE";
+  }
+  return "PSATD_ERR_UNKNOWN";
+}
+
+const char* psatd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+// Device FFT building blocks for gfx950: FP64 complex arithmetic, small DFTs
+// with compile-time twiddles, and a Stockham autosort stage over lines held
+// in LDS.  Storage precision is chosen by the callers; arithmetic here is FP64
+// (full rate on CDNA4, the same as unpacked FP32).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace psatd {
+
+// ------------------------------------------------------------------ complex
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) {
+  return make_double2(a.x * s, a.y * s);
+}
+// a * (SIGN * i)
+template <int SIGN>
+__device__ __forceinline__ double2 mul_si(double2 a) {
+  if constexpr (SIGN > 0) return make_double2(-a.y, a.x);
+  else return make_double2(a.y, -a.x);
+}
+
+// ------------------------------------------------------------------ static_for
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// exp(2 pi i m / 16) for m in [0, 16), built from three constants so that
+// the table is exactly symmetric.
+constexpr double kC1 = 0.92387953251128674;  // cos(pi/8)
+constexpr double kS1 = 0.38268343236508978;  // sin(pi/8)
+constexpr double kR2 = 0.70710678118654752;  // sqrt(1/2)
+
+constexpr double cos16(int m) {
+  constexpr double t[16] = {1.0, kC1, kR2, kS1, 0.0, -kS1, -kR2, -kC1,
+                            -1.0, -kC1, -kR2, -kS1, 0.0, kS1, kR2, kC1};
+  return t[m];
+}
+constexpr double sin16(int m) {
+  constexpr double t[16] = {0.0, kS1, kR2, kC1, 1.0, kC1, kR2, kS1,
+                            0.0, -kS1, -kR2, -kC1, -1.0, -kC1, -kR2, -kS1};
+  return t[m];
+}
+
+// a * exp(SIGN * 2 pi i M / N) for N dividing 16.
+template <int N, int M, int SIGN>
+__device__ __forceinline__ double2 twc(double2 a) {
+  constexpr int m = ((M % N) + N) % N;
+  constexpr int q = m * (16 / N);
+  if constexpr (q == 0) return a;
+  else if constexpr (q == 4) return mul_si<SIGN>(a);
+  else if constexpr (q == 8) return make_double2(-a.x, -a.y);
+  else if constexpr (q == 12) return mul_si<-SIGN>(a);
+  else return cmul(a, make_double2(cos16(q), SIGN * sin16(q)));
+}
+
+// ------------------------------------------------------------------ small DFTs
+// In-place DFT of length R: v[k] <- sum_n v[n] exp(SIGN 2 pi i n k / R).
+template <int R, int SIGN>
+struct DFT;
+
+template <int SIGN>
+struct DFT<2, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    const double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int SIGN>
+struct DFT<3, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    constexpr double kH = 0.86602540378443865;  // sqrt(3)/2
+    const double2 t = cadd(v[1], v[2]);
+    const double2 u = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+    const double2 w = mul_si<SIGN>(cscale(csub(v[1], v[2]), kH));
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(u, w);
+    v[2] = csub(u, w);
+  }
+};
+
+template <int SIGN>
+struct DFT<4, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) {
+    const double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const double2 c = cadd(v[1], v[3]), d = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  }
+};
+
+// N = R1 R2 with n = R2 n1 + n2 and k = k1 + R1 k2:
+//   X[k1 + R1 k2] = sum_n2 W_N^{n2 k1} W_R2^{n2 k2} sum_n1 x[R2 n1 + n2] W_R1^{n1 k1}.
+template <int R1, int R2, int SIGN>
+__device__ __forceinline__ void dft_split(double2* x) {
+  constexpr int N = R1 * R2;
+  double2 a[R2][R1];
+  static_for<0, R2>([&](auto n2c) __attribute__((always_inline)) {
+    constexpr int n2 = decltype(n2c)::value;
+    double2 t[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n1] = x[R2 * n1 + n2];
+    DFT<R1, SIGN>::run(t);
+    static_for<0, R1>([&](auto k1c) __attribute__((always_inline)) {
+      constexpr int k1 = decltype(k1c)::value;
+      a[n2][k1] = twc<N, n2 * k1, SIGN>(t[k1]);
+    });
+  });
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    double2 t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = a[n2][k1];
+    DFT<R2, SIGN>::run(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = t[k2];
+  }
+}
+
+template <int SIGN>
+struct DFT<8, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) { dft_split<2, 4, SIGN>(v); }
+};
+
+template <int SIGN>
+struct DFT<16, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) { dft_split<4, 4, SIGN>(v); }
+};
+
+// ------------------------------------------------------------------ Stockham stage
+// One radix-R stage over nl lines of length L stored in LDS (line stride LS,
+// in place).  Ns is the product of the radices already applied.  Butterfly
+// j of a line reads x[j + q L/R], multiplies by w^q with
+// w = exp(SIGN 2 pi i (j mod Ns) / (Ns R)), applies DFT<R> and writes
+// y[(j - j mod Ns) R + j mod Ns + q Ns].  Each thread handles at most
+// MAXPTS / R butterflies (the planner guarantees that).
+template <int R, int SIGN, int MAXPTS>
+__device__ __forceinline__ void lds_stage(double2* lds, int L, int nl, int LS, int Ns,
+                                          const double2* __restrict__ tw) {
+  constexpr int BPT = MAXPTS / R;
+  const int nb = L / R;
+  const int total = nb * nl;
+  const int T = blockDim.x;
+  const int twstride = L / (Ns * R);
+  double2 v[BPT][R];
+  int obase[BPT];
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int b = threadIdx.x + t * T;
+    if (b < total) {
+      const int line = b / nb;
+      const int j = b - line * nb;
+      const double2* src = lds + line * LS + j;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[t][q] = src[q * nb];
+      const int k = j % Ns;
+      obase[t] = line * LS + (j - k) * R + k;
+      if (k != 0) {
+        double2 w = tw[k * twstride];
+        if constexpr (SIGN > 0) w.y = -w.y;
+        double2 wq = w;
+        v[t][1] = cmul(v[t][1], w);
+#pragma unroll
+        for (int q = 2; q < R; ++q) {
+          wq = cmul(wq, w);
+          v[t][q] = cmul(v[t][q], wq);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int b = threadIdx.x + t * T;
+    if (b < total) {
+      DFT<R, SIGN>::run(v[t]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[obase[t] + q * Ns] = v[t][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Full complex FFT (unnormalized) of nl lines in LDS, radices from a plan in
+// global memory.  SIGN = -1 forward, +1 inverse.  Ends with a barrier.
+template <int SIGN, int MAXPTS>
+__device__ __forceinline__ void fft_lds(double2* lds, int nl, int LS, const FFTPlanDev* __restrict__ f) {
+  const int L = f->n;
+  const int ns = f->nstages;
+  const double2* tw = f->tw;
+  int Ns = 1;
+  for (int s = 0; s < ns; ++s) {
+    const int R = f->radix[s];
+    if (MAXPTS >= 16 && R == 16) {
+      if constexpr (MAXPTS >= 16) lds_stage<16, SIGN, MAXPTS>(lds, L, nl, LS, Ns, tw);
+    } else if (R == 8) {
+      lds_stage<8, SIGN, MAXPTS>(lds, L, nl, LS, Ns, tw);
+    } else if (R == 4) {
+      lds_stage<4, SIGN, MAXPTS>(lds, L, nl, LS, Ns, tw);
+    } else if (R == 3) {
+      lds_stage<3, SIGN, MAXPTS>(lds, L, nl, LS, Ns, tw);
+    } else {
+      lds_stage<2, SIGN, MAXPTS>(lds, L, nl, LS, Ns, tw);
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace psatd

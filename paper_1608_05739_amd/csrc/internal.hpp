@@ -1,0 +1,72 @@
+// Device-side descriptors shared by the host planner and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace psatd {
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxComp = 11;  // Ex Ey Ez Bx By Bz Jx Jy Jz rho_old rho_new
+
+// Component slots in the workspace and in FieldPtrs.
+enum Comp : int {
+  kEx = 0, kEy, kEz, kBx, kBy, kBz, kJx, kJy, kJz, kRhoOld, kRhoNew
+};
+
+enum SourceForm : int { kVacuum = 0, kRho = 1, kJForm = 2 };
+
+// A complex FFT of length n factorized into radices (applied in order,
+// Stockham autosort).  tw[m] = exp(-2 pi i m / n) in FP64, m in [0, n).
+struct FFTPlanDev {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  const double2* tw;
+};
+
+// One periodic patch.  Real arrays are [nz][ny][nx] (ny = 1 in 2D).  The
+// workspace holds, per patch, one block of comp_stride complex elements per
+// input component; after the x pass the x axis is halved to mx = nx/2 complex
+// columns, column 0 carrying the DC and Nyquist planes packed as re + i*im.
+//   2D spectra  [kx][z]           (lines along z contiguous)
+//   3D spectra  [z][kx][y] after the x pass, [kx][y][z] after the y pass.
+struct PatchDev {
+  int ndim;
+  int nx, ny, nz, mx;
+  int pad0;
+  double dt;
+  double inv_n;           // 1 / (nx ny nz), folded into the update
+  long long off_real;     // element offset in the caller's component buffers
+  long long off_spec;     // complex-element offset of this patch's first component
+  long long comp_stride;  // complex elements per component block (mx ny nz)
+  const double* kx;       // [mx]  k_x of packed column j (column 0: k_x = 0)
+  const double* ky;       // [ny]
+  const double* kz;       // [nz]
+  const double2* post;    // [mx]  exp(-2 pi i j / nx), r2c post-twiddles
+  FFTPlanDev fx;          // length mx
+  FFTPlanDev fy;          // length ny (3D)
+  FFTPlanDev fz;          // length nz
+};
+
+// A unit of work: `count` consecutive lines starting at `first` of component
+// `comp` of patch `patch` (comp = -1 where a kernel handles all components).
+struct WorkItem {
+  int patch;
+  int first;
+  int count;
+  int comp;
+};
+
+// Caller field pointers (real arrays), indexed by Comp.
+struct FieldPtrs {
+  void* f[kMaxComp];
+};
+
+struct Physics {
+  double c;
+  double eps0;
+};
+
+}  // namespace psatd

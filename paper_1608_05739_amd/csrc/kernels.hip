@@ -1,0 +1,628 @@
+// PSATD kernels for gfx950.
+//
+// Data path of one step (2D; 3D adds the y passes):
+//   x pass   real rows -> r2c FFT along x (half-length complex FFT + post
+//            twiddle) -> spectra with the lines of the next axis contiguous
+//   z pass   fused: forward FFT of every input along z, per-mode analytic
+//            update, inverse FFT of E' and B' along z, all in one launch
+//   x pass   inverse: pre-twiddle + inverse complex FFT -> real rows of E, B
+// Storage is FP32 or FP64 (template S); FFT and update arithmetic is FP64.
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+#include "kernels.hpp"
+#include "update.hpp"
+
+namespace psatd {
+
+template <typename S>
+struct Vec2;
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+template <typename V>
+__device__ __forceinline__ V from_d2(double2 v);
+template <>
+__device__ __forceinline__ float2 from_d2<float2>(double2 v) {
+  return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+template <>
+__device__ __forceinline__ double2 from_d2<double2>(double2 v) {
+  return v;
+}
+
+// ------------------------------------------------------------------ addressing
+// Strided ("tile") side of a line pass: element n of line l sits at
+// (l % A) + (l / A) * B + n * C (complex elements), so R consecutive lines are
+// R consecutive addresses whenever they share l / A.
+struct TileMap {
+  long long A, B, C;
+};
+
+__device__ __forceinline__ TileMap tile_map(int kind, const PatchDev* P) {
+  TileMap t;
+  if (kind == kXFwd || kind == kXInv) {
+    if (P->ndim == 2) {  // lines l = z ; spectra [kx][z]
+      t.A = P->nz; t.B = 0; t.C = P->nz;
+    } else {             // lines l = z*ny + y ; spectra [z][kx][y]
+      t.A = P->ny; t.B = (long long)P->mx * P->ny; t.C = P->ny;
+    }
+  } else {               // y passes: lines l = kx*nz + z ; spectra [kx][y][z]
+    t.A = P->nz; t.B = (long long)P->ny * P->nz; t.C = P->nz;
+  }
+  return t;
+}
+
+// Start of contiguous line l for the y passes ([z][kx][y]: l = kx*nz + z).
+__device__ __forceinline__ long long yline_start(const PatchDev* P, int l) {
+  const int z = l % P->nz;
+  const int kx = l / P->nz;
+  return ((long long)z * P->mx + kx) * P->ny;
+}
+
+// ------------------------------------------------------------------ r2c / c2r
+// After the forward complex FFT of z[m] = x[2m] + i x[2m+1] (length M):
+//   F[k] = E[k] + W^k O[k],  E = (Z[k] + conj Z[M-k])/2,  O = -i (Z[k] - conj Z[M-k])/2,
+//   F[M-k] = conj(E[k] - W^k O[k]),  W = exp(-2 pi i / (2M)).
+// Column 0 is packed as F[0] + i F[M] (both real).
+__device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
+  const int npair = M / 2 + 1;
+  for (int idx = threadIdx.x; idx < nl * npair; idx += blockDim.x) {
+    const int r = idx / npair;
+    const int k = idx - r * npair;
+    double2* row = lds + r * LS;
+    if (k == 0) {
+      const double2 z = row[0];
+      row[0] = make_double2(z.x + z.y, z.x - z.y);
+    } else {
+      const int kk = M - k;
+      const double2 a = row[k];
+      const double2 b = row[kk];
+      const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
+      const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
+      const double2 wo = cmul(post[k], o);
+      row[k] = cadd(e, wo);
+      if (kk != k) row[kk] = cconj(csub(e, wo));
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of r2c_post up to a factor 2:  Z'[k] = p + i conj(W^k) m,
+// Z'[M-k] = conj(p) + i W^k conj(m) with p = F[k] + conj F[M-k], m = F[k] - conj F[M-k];
+// column 0: Z'[0] = (F0 + FM) + i (F0 - FM).
+__device__ __forceinline__ void c2r_pre(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
+  const int npair = M / 2 + 1;
+  for (int idx = threadIdx.x; idx < nl * npair; idx += blockDim.x) {
+    const int r = idx / npair;
+    const int k = idx - r * npair;
+    double2* row = lds + r * LS;
+    if (k == 0) {
+      const double2 x = row[0];
+      row[0] = make_double2(x.x + x.y, x.x - x.y);
+    } else {
+      const int kk = M - k;
+      const double2 a = row[k];
+      const double2 b = row[kk];
+      const double2 p = make_double2(a.x + b.x, a.y - b.y);
+      const double2 m = make_double2(a.x - b.x, a.y + b.y);
+      const double2 w = post[k];
+      const double2 t1 = cmul(cconj(w), m);
+      const double2 t2 = cmul(w, cconj(m));
+      row[k] = make_double2(p.x - t1.y, p.y + t1.x);
+      if (kk != k) row[kk] = make_double2(p.x - t2.y, -p.y + t2.x);
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ line pass
+template <typename S, int KIND>
+__global__ void __launch_bounds__(kLineBlockMax)
+line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
+                 int nitems, FieldPtrs fields, S* __restrict__ ws) {
+  using V = typename Vec2<S>::type;
+  extern __shared__ double2 lds[];
+  constexpr int SIGN = (KIND == kXFwd || KIND == kYFwd || KIND == kZFwd) ? -1 : 1;
+  const int T = blockDim.x;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const PatchDev* P = patches + wi.patch;
+    const FFTPlanDev* F = (KIND == kXFwd || KIND == kXInv)   ? &P->fx
+                          : (KIND == kYFwd || KIND == kYInv) ? &P->fy
+                                                             : &P->fz;
+    const int L = F->n;
+    const int nl = wi.count;
+    const int l0 = wi.first;
+    const int LS = L;
+    const int total = nl * L;
+    V* spec = reinterpret_cast<V*>(ws) + P->off_spec + (long long)wi.comp * P->comp_stride;
+
+    // ---------------- load
+    if constexpr (KIND == kXFwd) {
+      const V* src = reinterpret_cast<const V*>(static_cast<const S*>(fields.f[wi.comp]) +
+                                                P->off_real);
+      for (int idx = threadIdx.x; idx < total; idx += T) {
+        const int r = idx / L;
+        const int n = idx - r * L;
+        lds[r * LS + n] = to_d2(src[(long long)(l0 + r) * L + n]);
+      }
+    } else if constexpr (KIND == kXInv || KIND == kYInv) {
+      const TileMap tm = tile_map(KIND, P);
+      for (int idx = threadIdx.x; idx < total; idx += T) {
+        const int n = idx / nl;
+        const int r = idx - n * nl;
+        const long long l = l0 + r;
+        lds[r * LS + n] = to_d2(spec[(l % tm.A) + (l / tm.A) * tm.B + n * tm.C]);
+      }
+    } else if constexpr (KIND == kYFwd) {
+      for (int idx = threadIdx.x; idx < total; idx += T) {
+        const int r = idx / L;
+        const int n = idx - r * L;
+        lds[r * LS + n] = to_d2(spec[yline_start(P, l0 + r) + n]);
+      }
+    } else {  // z lines, contiguous
+      const V* src = spec + (long long)l0 * L;
+      for (int idx = threadIdx.x; idx < total; idx += T) lds[idx] = to_d2(src[idx]);
+    }
+    __syncthreads();
+
+    if constexpr (KIND == kXInv) c2r_pre(lds, nl, LS, L, P->post);
+    fft_lds<SIGN, kMaxPts>(lds, nl, LS, F);
+    if constexpr (KIND == kXFwd) r2c_post(lds, nl, LS, L, P->post);
+
+    // ---------------- store
+    if constexpr (KIND == kXFwd || KIND == kYFwd) {
+      const TileMap tm = tile_map(KIND, P);
+      for (int idx = threadIdx.x; idx < total; idx += T) {
+        const int n = idx / nl;
+        const int r = idx - n * nl;
+        const long long l = l0 + r;
+        spec[(l % tm.A) + (l / tm.A) * tm.B + n * tm.C] = from_d2<V>(lds[r * LS + n]);
+      }
+    } else if constexpr (KIND == kXInv) {
+      V* dst = reinterpret_cast<V*>(static_cast<S*>(fields.f[wi.comp]) + P->off_real);
+      for (int idx = threadIdx.x; idx < total; idx += T) {
+        const int r = idx / L;
+        const int n = idx - r * L;
+        dst[(long long)(l0 + r) * L + n] = from_d2<V>(lds[r * LS + n]);
+      }
+    } else if constexpr (KIND == kYInv) {
+      for (int idx = threadIdx.x; idx < total; idx += T) {
+        const int r = idx / L;
+        const int n = idx - r * L;
+        spec[yline_start(P, l0 + r) + n] = from_d2<V>(lds[r * LS + n]);
+      }
+    } else {
+      V* dst = spec + (long long)l0 * L;
+      for (int idx = threadIdx.x; idx < total; idx += T) dst[idx] = from_d2<V>(lds[idx]);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ fused z pass
+// Input and output component groups.  In 2D (k_y = 0) the update splits into
+// the s-polarized set (Ey, Bx, Bz; Jy) and the p-polarized set (Ex, Ez, By;
+// Jx, Jz, rho), processed one after the other to halve the register state.
+template <int G, int SRC>
+struct Group;
+
+// 2D s-polarization
+template <int SRC>
+struct Group<0, SRC> {
+  static constexpr int nin = (SRC == kVacuum) ? 3 : 4;
+  static constexpr int in[4] = {kEy, kBx, kBz, kJy};
+  static constexpr int nout = 3;
+  static constexpr int out_slot[3] = {0, 1, 2};
+};
+// 2D p-polarization
+template <int SRC>
+struct Group<1, SRC> {
+  static constexpr int nin = (SRC == kVacuum) ? 3 : (SRC == kJForm ? 5 : 7);
+  static constexpr int in[7] = {kEx, kEz, kBy, kJx, kJz, kRhoOld, kRhoNew};
+  static constexpr int nout = 3;
+  static constexpr int out_slot[3] = {0, 1, 2};
+};
+// 3D: everything couples
+template <int SRC>
+struct Group<2, SRC> {
+  static constexpr int nin = (SRC == kVacuum) ? 6 : (SRC == kJForm ? 9 : 11);
+  static constexpr int in[11] = {kEx, kEy, kEz, kBx, kBy, kBz, kJx, kJy, kJz, kRhoOld, kRhoNew};
+  static constexpr int nout = 6;
+  static constexpr int out_slot[6] = {0, 1, 2, 3, 4, 5};
+};
+
+template <typename S, int G, int SRC, int MPT>
+__device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& wi, S* ws,
+                                            const Physics& ph, double2* lds) {
+  using V = typename Vec2<S>::type;
+  using Gr = Group<G, SRC>;
+  constexpr int NIN = Gr::nin;
+  const int T = blockDim.x;
+  const int nz = P->nz;
+  const int W = wi.count;
+  const int nmodes = W * nz;
+  V* base = reinterpret_cast<V*>(ws) + P->off_spec + (long long)wi.first * nz;
+  const long long cs = P->comp_stride;
+  const FFTPlanDev* F = &P->fz;
+
+  V reg[NIN][MPT];
+  // Forward transforms of the group's inputs.  The slot loop is a runtime loop
+  // so that the FFT code is instantiated once; the register slot is then
+  // selected by a compile-time compare chain (no dynamic register indexing).
+#pragma nounroll
+  for (int slot = 0; slot < NIN; ++slot) {
+    const V* src = base + Gr::in[slot] * cs;
+    for (int idx = threadIdx.x; idx < nmodes; idx += T) lds[idx] = to_d2(src[idx]);
+    __syncthreads();
+    fft_lds<-1, kMaxPtsFused>(lds, W, nz, F);
+    static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int sl = decltype(sc)::value;
+      if (slot == sl) {
+#pragma unroll
+        for (int m = 0; m < MPT; ++m) {
+          const int idx = threadIdx.x + m * T;
+          if (idx < nmodes) reg[sl][m] = from_d2<V>(lds[idx]);
+        }
+      }
+    });
+    __syncthreads();
+  }
+
+  // per-mode update
+  const double dt = P->dt;
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    const int idx = threadIdx.x + m * T;
+    if (idx < nmodes) {
+      const int line = wi.first + idx / nz;
+      const int iz = idx % nz;
+      double kx, ky;
+      if (P->ndim == 2) {
+        kx = P->kx[line];
+        ky = 0.0;
+      } else {
+        kx = P->kx[line / P->ny];
+        ky = P->ky[line % P->ny];
+      }
+      const double kz = P->kz[iz];
+      const double K = sqrt(kx * kx + ky * ky + kz * kz);
+      const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
+      double2 E[3] = {}, B[3] = {}, J[3] = {};
+      double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+      static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int slot = decltype(sc)::value;
+        constexpr int comp = Gr::in[slot];
+        const double2 v = to_d2(reg[slot][m]);
+        if constexpr (comp < 3) E[comp] = v;
+        else if constexpr (comp < 6) B[comp - 3] = v;
+        else if constexpr (comp < 9) J[comp - 6] = v;
+        else if constexpr (comp == kRhoOld) ro = v;
+        else rn = v;
+      });
+      double2 Eo[3], Bo[3];
+      update_mode<SRC>(kx, ky, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+      static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int comp = Gr::in[Gr::out_slot[o]];
+        if constexpr (comp < 3) reg[Gr::out_slot[o]][m] = from_d2<V>(Eo[comp]);
+        else reg[Gr::out_slot[o]][m] = from_d2<V>(Bo[comp - 3]);
+      });
+    }
+    // keep the modes' updates from being interleaved (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // Inverse transforms of the outputs, written back over the input slots.
+#pragma nounroll
+  for (int o = 0; o < Gr::nout; ++o) {
+    const int slot = Gr::out_slot[o];
+    static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int sl = decltype(sc)::value;
+      if (slot == sl) {
+#pragma unroll
+        for (int m = 0; m < MPT; ++m) {
+          const int idx = threadIdx.x + m * T;
+          if (idx < nmodes) lds[idx] = to_d2(reg[sl][m]);
+        }
+      }
+    });
+    __syncthreads();
+    fft_lds<1, kMaxPtsFused>(lds, W, nz, F);
+    V* dst = base + Gr::in[slot] * cs;
+    for (int idx = threadIdx.x; idx < nmodes; idx += T) dst[idx] = from_d2<V>(lds[idx]);
+    __syncthreads();
+  }
+}
+
+template <typename S, int DIM, int SRC, int MPT>
+__global__ void __launch_bounds__(kFusedBlock)
+fused_z_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
+               int nitems, S* __restrict__ ws, Physics ph) {
+  extern __shared__ double2 lds[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const PatchDev* P = patches + wi.patch;
+    if constexpr (DIM == 2) {
+      fused_group<S, 0, SRC, MPT>(P, wi, ws, ph, lds);
+      fused_group<S, 1, SRC, MPT>(P, wi, ws, ph, lds);
+    } else {
+      fused_group<S, 2, SRC, MPT>(P, wi, ws, ph, lds);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ plain update
+template <typename S, int SRC>
+__global__ void __launch_bounds__(256)
+update_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
+              int nitems, S* __restrict__ ws, Physics ph) {
+  using V = typename Vec2<S>::type;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[it];
+    const PatchDev* P = patches + wi.patch;
+    V* base = reinterpret_cast<V*>(ws) + P->off_spec;
+    const long long cs = P->comp_stride;
+    const int nz = P->nz;
+    const double dt = P->dt;
+    for (int j = threadIdx.x; j < wi.count; j += blockDim.x) {
+      const long long idx = (long long)wi.first + j;
+      const long long line = idx / nz;
+      const int iz = static_cast<int>(idx - line * nz);
+      double kx, ky;
+      if (P->ndim == 2) {
+        kx = P->kx[line];
+        ky = 0.0;
+      } else {
+        kx = P->kx[line / P->ny];
+        ky = P->ky[line % P->ny];
+      }
+      const double kz = P->kz[iz];
+      const double K = sqrt(kx * kx + ky * ky + kz * kz);
+      const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
+      double2 E[3], B[3], J[3] = {};
+      double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        E[i] = to_d2(base[(kEx + i) * cs + idx]);
+        B[i] = to_d2(base[(kBx + i) * cs + idx]);
+      }
+      if constexpr (SRC != kVacuum) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) J[i] = to_d2(base[(kJx + i) * cs + idx]);
+      }
+      if constexpr (SRC == kRho) {
+        ro = to_d2(base[kRhoOld * cs + idx]);
+        rn = to_d2(base[kRhoNew * cs + idx]);
+      }
+      double2 Eo[3], Bo[3];
+      update_mode<SRC>(kx, ky, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        base[(kEx + i) * cs + idx] = from_d2<V>(Eo[i]);
+        base[(kBx + i) * cs + idx] = from_d2<V>(Bo[i]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ tables (FP64)
+__global__ void twiddle_kernel(double2* tw, int n, int count) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < count) {
+    double s, c;
+    sincospi(2.0 * static_cast<double>(m) / static_cast<double>(n), &s, &c);
+    tw[m] = make_double2(c, -s);
+  }
+}
+
+// k_j = 2 pi m_j / (n d) in fftfreq order, the Nyquist index (even n) -> 0.
+// packed_x: entries j = 0..count-1 of the halved x axis, entry 0 standing for
+// both the DC and the Nyquist columns (k = 0 for both).  With Fornberg weights
+// C_l (nf = p/2 of them) the order-p wavevector
+// k_p = sum_l C_l (2/d) sin((2l - 1) k d / 2) replaces k.
+__global__ void ktable_kernel(double* k, int n, double d, int count, int packed_x,
+                              const double* __restrict__ fornberg, int nf) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  int m = (j < (n + 1) / 2) ? j : j - n;
+  const bool nyquist = (n % 2 == 0) && (j == n / 2);
+  if (packed_x) m = j;
+  constexpr double kTwoPi = 6.283185307179586476925286766559;
+  double kv = kTwoPi * static_cast<double>(m) / (static_cast<double>(n) * d);
+  if (nf > 0) {
+    double acc = 0.0;
+    for (int l = 1; l <= nf; ++l) acc += fornberg[l - 1] * (2.0 / d) * sin((2 * l - 1) * kv * d * 0.5);
+    kv = acc;
+  }
+  if (nyquist || (packed_x && j == 0)) kv = 0.0;
+  k[j] = kv;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename S>
+static hipError_t line_dispatch(int kind, const LaunchShape& sh, hipStream_t stream,
+                                const PatchDev* p, const WorkItem* it, int n, const FieldPtrs& f,
+                                S* ws) {
+  switch (kind) {
+    case kXFwd:
+      hipLaunchKernelGGL((line_pass_kernel<S, kXFwd>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
+                         stream, p, it, n, f, ws);
+      break;
+    case kXInv:
+      hipLaunchKernelGGL((line_pass_kernel<S, kXInv>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
+                         stream, p, it, n, f, ws);
+      break;
+    case kYFwd:
+      hipLaunchKernelGGL((line_pass_kernel<S, kYFwd>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
+                         stream, p, it, n, f, ws);
+      break;
+    case kYInv:
+      hipLaunchKernelGGL((line_pass_kernel<S, kYInv>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
+                         stream, p, it, n, f, ws);
+      break;
+    case kZFwd:
+      hipLaunchKernelGGL((line_pass_kernel<S, kZFwd>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
+                         stream, p, it, n, f, ws);
+      break;
+    default:
+      hipLaunchKernelGGL((line_pass_kernel<S, kZInv>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
+                         stream, p, it, n, f, ws);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_line_pass(int kind, int precision, const LaunchShape& sh, hipStream_t stream,
+                            const PatchDev* patches, const WorkItem* items, int nitems,
+                            const FieldPtrs& fields, void* ws) {
+  if (precision == 0)
+    return line_dispatch<float>(kind, sh, stream, patches, items, nitems, fields,
+                                static_cast<float*>(ws));
+  return line_dispatch<double>(kind, sh, stream, patches, items, nitems, fields,
+                               static_cast<double*>(ws));
+}
+
+// Modes per thread compiled for each (precision, ndim): the transformed inputs
+// of a group stay in registers, so MPT * inputs * sizeof(complex) is bounded.
+bool fused_supported(int precision, int ndim, int mpt) {
+  if (precision == 0) return (ndim == 2 && mpt == 8) || (ndim == 3 && mpt == 4);
+  return (ndim == 2 && mpt == 4) || (ndim == 3 && mpt == 2);
+}
+
+template <typename S, int DIM, int MPT>
+static hipError_t fused_dispatch(int src, const LaunchShape& sh, hipStream_t stream,
+                                 const PatchDev* p, const WorkItem* it, int n, S* ws, Physics ph) {
+  switch (src) {
+    case kVacuum:
+      hipLaunchKernelGGL((fused_z_kernel<S, DIM, kVacuum, MPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, ws, ph);
+      break;
+    case kRho:
+      hipLaunchKernelGGL((fused_z_kernel<S, DIM, kRho, MPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, ws, ph);
+      break;
+    default:
+      hipLaunchKernelGGL((fused_z_kernel<S, DIM, kJForm, MPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, ws, ph);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_z(int precision, int ndim, int src, int mpt, const LaunchShape& sh,
+                          hipStream_t stream, const PatchDev* patches, const WorkItem* items,
+                          int nitems, void* ws, Physics ph) {
+  if (!fused_supported(precision, ndim, mpt)) return hipErrorInvalidValue;
+  if (precision == 0) {
+    if (ndim == 2)
+      return fused_dispatch<float, 2, 8>(src, sh, stream, patches, items, nitems,
+                                         static_cast<float*>(ws), ph);
+    return fused_dispatch<float, 3, 4>(src, sh, stream, patches, items, nitems,
+                                       static_cast<float*>(ws), ph);
+  }
+  if (ndim == 2)
+    return fused_dispatch<double, 2, 4>(src, sh, stream, patches, items, nitems,
+                                        static_cast<double*>(ws), ph);
+  return fused_dispatch<double, 3, 2>(src, sh, stream, patches, items, nitems,
+                                      static_cast<double*>(ws), ph);
+}
+
+template <typename S>
+static hipError_t update_dispatch(int src, const LaunchShape& sh, hipStream_t stream,
+                                  const PatchDev* p, const WorkItem* it, int n, S* ws, Physics ph) {
+  switch (src) {
+    case kVacuum:
+      hipLaunchKernelGGL((update_kernel<S, kVacuum>), dim3(sh.grid), dim3(sh.block), 0, stream, p,
+                         it, n, ws, ph);
+      break;
+    case kRho:
+      hipLaunchKernelGGL((update_kernel<S, kRho>), dim3(sh.grid), dim3(sh.block), 0, stream, p, it,
+                         n, ws, ph);
+      break;
+    default:
+      hipLaunchKernelGGL((update_kernel<S, kJForm>), dim3(sh.grid), dim3(sh.block), 0, stream, p,
+                         it, n, ws, ph);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int precision, int src, const LaunchShape& sh, hipStream_t stream,
+                         const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
+                         Physics ph) {
+  if (precision == 0)
+    return update_dispatch<float>(src, sh, stream, patches, items, nitems,
+                                  static_cast<float*>(ws), ph);
+  return update_dispatch<double>(src, sh, stream, patches, items, nitems,
+                                 static_cast<double*>(ws), ph);
+}
+
+hipError_t launch_twiddles(double2* tw, int n, int count, hipStream_t stream) {
+  const int b = 256;
+  hipLaunchKernelGGL(twiddle_kernel, dim3((count + b - 1) / b), dim3(b), 0, stream, tw, n, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ktable(double* k, int n, double d, int count, int packed_x,
+                         const double* fornberg, int nfornberg, hipStream_t stream) {
+  const int b = 256;
+  hipLaunchKernelGGL(ktable_kernel, dim3((count + b - 1) / b), dim3(b), 0, stream, k, n, d, count,
+                     packed_x, fornberg, nfornberg);
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t set_attrs_for() {
+  const int lim = 160 * 1024;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* fn) {
+    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (r != hipSuccess) e = r;
+  };
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kXFwd>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kXInv>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kYFwd>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kYInv>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kZFwd>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kZInv>));
+  return e;
+}
+
+template <typename S, int DIM, int MPT>
+static hipError_t set_fused_attrs() {
+  const int lim = 160 * 1024;
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* fn) {
+    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (r != hipSuccess) e = r;
+  };
+  set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kVacuum, MPT>));
+  set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kRho, MPT>));
+  set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kJForm, MPT>));
+  return e;
+}
+
+hipError_t configure_kernel_attributes() {
+  hipError_t e = hipSuccess;
+  hipError_t r;
+  if ((r = set_attrs_for<float>()) != hipSuccess) e = r;
+  if ((r = set_attrs_for<double>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<float, 2, 8>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<float, 3, 4>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<double, 2, 4>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<double, 3, 2>()) != hipSuccess) e = r;
+  return e;
+}
+
+}  // namespace psatd

@@ -1,0 +1,133 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative L2 over E and B):
+  FP64 storage   1e-12 (the FP64 oracle target)
+  FP32 storage   1e-5  (the FP32 target).  The FP32 path rounds to FP32 when
+                 it stores to HBM, so the inputs the oracle sees are the same
+                 FP32-rounded arrays, upcast.
+Sizes span several tiles and ragged tails (line counts not multiples of the
+tile, radix-3 factors, length-1 x transforms).
+"""
+
+import numpy as np
+import pytest
+
+import fixtures
+from gpu_support import compare, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _w(index, shape, steps):
+    return fixtures.workload(index, shape=shape, steps=steps)
+
+
+# ----------------------------------------------------------------- workload 0, full size
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp64", "fused"),
+                                            ("fp32", "fused"), ("fp32", "plain")])
+def test_workload0_vacuum_128(precision, path):
+    w = fixtures.workload(0)
+    say(f"workload0 {precision} {path} 128x128 x {w.steps} steps")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
+    say(f"  rel L2 = {err:.3e}")
+    assert err < TOL[precision]
+
+
+# ----------------------------------------------------------------- 2D, sources, ragged
+SHAPES_2D = [(48, 64), (6, 8), (12, 18), (18, 12), (96, 64), (64, 96), (2, 4), (4, 2), (36, 24)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_2D)
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp64", "fused"),
+                                            ("fp32", "fused")])
+def test_2d_sources_rho(shape, precision, path):
+    w = _w(1, shape, 6)
+    say(f"2d rho {shape} {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
+    say(f"  rel L2 = {err:.3e}")
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("shape", [(48, 64), (12, 18)])
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "fused")])
+def test_2d_sources_jform(shape, precision, path):
+    w = _w(1, shape, 5)
+    say(f"2d J-form {shape} {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps, form="J"),
+                  run_oracle(w, precision, w.steps, form="J"))
+    assert err < TOL[precision]
+
+
+# ----------------------------------------------------------------- 3D
+SHAPES_3D = [(8, 6, 12), (12, 8, 18), (16, 16, 16), (6, 12, 8)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_3D)
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp64", "fused"),
+                                            ("fp32", "fused")])
+def test_3d_sources_rho(shape, precision, path):
+    w = _w(2, shape, 4)
+    say(f"3d rho {shape} {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
+    say(f"  rel L2 = {err:.3e}")
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp32", "fused")])
+def test_3d_vacuum_plane_waves(precision, path):
+    w = fixtures.workload(4, shape=(16, 24, 32), steps=6)
+    w.sources = False
+    say(f"3d vacuum packets {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
+    assert err < TOL[precision]
+
+
+@pytest.mark.parametrize("order", [2, 8, 128])
+def test_order_p(order):
+    w = _w(1, (32, 48), 4)
+    say(f"order {order}")
+    err = compare(run_gpu(w, "fp64", "plain", w.steps, order=order),
+                  run_oracle(w, "fp64", w.steps, order=order))
+    assert err < TOL["fp64"]
+
+
+# ----------------------------------------------------------------- batched patches
+def test_batched_patches_workload3_subset():
+    w = fixtures.workload(3, npatches=24, steps=3)
+    say(f"batched 24 patches, {w.cells} cells")
+    for precision, path in (("fp32", "fused"), ("fp64", "plain")):
+        err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
+        say(f"  {precision} {path}: rel L2 = {err:.3e}")
+        assert err < TOL[precision]
+
+
+def test_batched_patch_equals_patch_alone():
+    w = fixtures.workload(3, npatches=6, steps=2)
+    E_all, B_all = run_gpu(w, "fp32", "fused", 2)
+    for p in (0, 3, 5):
+        Ep, Bp = run_gpu(w, "fp32", "fused", 2, patches=[w.patches[p]], E0=[w.E0[p]], B0=[w.B0[p]],
+                         schedule=[None])
+        for c in range(3):
+            assert np.array_equal(E_all[p][c], Ep[0][c])
+            assert np.array_equal(B_all[p][c], Bp[0][c])
+
+
+# ----------------------------------------------------------------- graph replay
+def test_graph_replay_equals_eager():
+    w = fixtures.workload(0, steps=10)
+    a = run_gpu(w, "fp32", "fused", 10, graph=False)
+    b = run_gpu(w, "fp32", "fused", 10, graph=True)
+    for pa, pb in zip(a[0] + a[1], b[0] + b[1]):
+        for x, y in zip(pa, pb):
+            assert np.array_equal(x, y)
+
+
+def test_repeated_runs_bitwise_identical():
+    w = _w(1, (64, 96), 3)
+    a = run_gpu(w, "fp32", "fused", 3)
+    b = run_gpu(w, "fp32", "fused", 3)
+    for pa, pb in zip(a[0] + a[1], b[0] + b[1]):
+        for x, y in zip(pa, pb):
+            assert np.array_equal(x, y)

@@ -1,0 +1,111 @@
+"""The C-ABI library loads and exports every symbol include/psatd.h declares.
+
+No compute call is made: validation errors are reported on the host before
+any HIP call, so they can be checked without a GPU.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1608_05739_amd as pk
+from paper_1608_05739_amd import _binding as b
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "psatd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psatd_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pk.LIBRARY_PATH):
+        pytest.fail("libpsatd.so is not built; run __graft_entry__.build()")
+    return pk.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("psatd_plan", "psatd_push", "psatd_destroy", "psatd_workspace_size",
+                 "psatd_set_workspace", "psatd_status_string", "psatd_last_error"):
+        assert must in names
+    assert set(names) == set(b.EXPORTED_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code, name in b.STATUS_NAMES.items():
+        assert lib.psatd_status_string(code).decode() == name
+
+
+def _desc(n=(8, 1, 8), d=(1.0, 1.0, 1.0), dt=0.5, ndim=2, offset=0):
+    pd = b.PatchDesc()
+    pd.ndim = ndim
+    pd.n = (ctypes.c_int64 * 3)(*n)
+    pd.d = (ctypes.c_double * 3)(*d)
+    pd.dt = dt
+    pd.offset = offset
+    return pd
+
+
+def _cfg(**kw):
+    c = b.Config()
+    c.precision, c.source_mode, c.path, c.order = 0, 0, 0, 0
+    c.c, c.eps0, c.flags = 1.0, 1.0, 0
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("desc,cfg,expect", [
+    (_desc(n=(10, 1, 8)), _cfg(), -2),          # 10 = 2 * 5: radix 5 unsupported
+    (_desc(n=(7, 1, 8)), _cfg(), -2),           # odd x length
+    (_desc(n=(8, 1, 8192)), _cfg(), -2),        # longer than 4096
+    (_desc(n=(8, 2, 8)), _cfg(), -1),           # 2D with ny != 1
+    (_desc(dt=0.0), _cfg(), -1),                # dt must be > 0
+    (_desc(d=(1.0, 1.0, -1.0)), _cfg(), -1),    # spacing must be > 0
+    (_desc(offset=3), _cfg(), -1),              # odd offset
+    (_desc(), _cfg(precision=5), -1),
+    (_desc(), _cfg(source_mode=9), -1),
+    (_desc(), _cfg(order=3), -1),               # odd order
+    (_desc(), _cfg(c=0.0), -1),
+    (_desc(), _cfg(flags=0x100), -1),
+])
+def test_plan_validation_on_host(lib, desc, cfg, expect):
+    out = ctypes.c_void_p()
+    st = lib.psatd_plan(ctypes.byref(cfg), ctypes.byref(desc), 1, 0, ctypes.byref(out))
+    assert st == expect, lib.psatd_last_error().decode()
+    assert out.value is None
+    assert lib.psatd_last_error().decode() != ""
+
+
+def test_overlapping_patches_rejected(lib):
+    descs = (b.PatchDesc * 2)(_desc(offset=0), _desc(offset=32))
+    out = ctypes.c_void_p()
+    st = lib.psatd_plan(ctypes.byref(_cfg()), descs, 2, 0, ctypes.byref(out))
+    assert st == -1 and "overlap" in lib.psatd_last_error().decode()
+
+
+def test_null_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.psatd_plan(None, ctypes.byref(_desc()), 1, 0, ctypes.byref(out)) == -1
+    assert lib.psatd_plan(ctypes.byref(_cfg()), None, 1, 0, ctypes.byref(out)) == -1
+    assert lib.psatd_plan(ctypes.byref(_cfg()), ctypes.byref(_desc()), 0, 0, ctypes.byref(out)) == -1
+    assert lib.psatd_push(None, None, 1, None) == -1
+    assert lib.psatd_destroy(None) == 0
+    n = ctypes.c_size_t()
+    assert lib.psatd_workspace_size(None, ctypes.byref(n)) == -1
+
+
+def test_package_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        b.load_library(str(tmp_path / "missing.so"))
