@@ -1,0 +1,274 @@
+"""Benchmark of the PSATD field step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
+
+A step is one full pass of the hot path (x r2c FFT of every input, fused z
+pass with the per-mode update, x c2r FFT of E and B) over the workload's
+synthetic fields, inputs resident in HBM.  Workload 1 (default): 2D 4096 x
+4096, J and rho sources (rho form), FP32 storage.  Prints ONE JSON line on
+stdout; progress goes to stderr.
+
+The line also reports, on the same workload: the plain FP64 path, the
+per-pass durations (HIP events on the launch stream), the roofline of the
+dominant kernel, a one-step parity check against the FP64 oracle, and the
+oracle's own throughput on the host cores (cpu_baseline).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PSATD cell-steps/s + HBM GB/s (% peak), FP32 batched vs FP64 plain, 1 GPU"
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_1608_05739_amd", "csrc")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counters, if they still
+    describe the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(f"{workload}:{kernel}")
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def build_inputs(index, steps, npatches=None):
+    import fixtures
+
+    log(f"[bench] generating workload {index} inputs ...")
+    t = time.time()
+    w = fixtures.workload(index, steps=steps, npatches=npatches)
+    log(f"[bench]   {w.name}: {w.cells} cells, {len(w.patches)} patch(es), {time.time() - t:.1f} s")
+    return w
+
+
+def device_fields(w, plan, dtype):
+    import torch
+
+    def pack(arrs):
+        flat = np.zeros(plan.total_elements, dtype=dtype)
+        for off, a in zip(plan.offsets, arrs):
+            flat[off:off + a.size] = np.asarray(a, dtype=dtype).ravel()
+        return torch.from_numpy(flat).to("cuda:0")
+
+    E = [pack([w.E0[p][c] for p in range(len(w.patches))]) for c in range(3)]
+    B = [pack([w.B0[p][c] for p in range(len(w.patches))]) for c in range(3)]
+    J = ro = rn = None
+    if w.sources:
+        srcs = [w.schedule[p].sources(0, dtype=dtype) for p in range(len(w.patches))]
+        J = [pack([s[0][c] for s in srcs]) for c in range(3)]
+        ro = pack([s[1] for s in srcs])
+        rn = pack([s[2] for s in srcs])
+    return E, B, J, ro, rn
+
+
+def time_steps(plan, E, B, J, ro, rn, steps, warmup, vacuum_batch):
+    """Wall-clock seconds of exactly `steps` steps, synchronized on both sides."""
+    import torch
+
+    def run(n):
+        if vacuum_batch:
+            plan.push(E, B, steps=n)
+        else:
+            for _ in range(n):
+                plan.push(E, B, J, ro, rn, steps=1)
+
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s, rounded_dtype):
+    """The FP64 oracle on the host cores, on the first steps of the same workload."""
+    import oracle
+
+    workers = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cells = 0
+    steps_done = 0
+    t0 = time.perf_counter()
+    first = None
+    for pi, p in enumerate(w.patches):
+        E = [np.asarray(a, rounded_dtype).astype(np.float64) for a in w.E0[pi]]
+        B = [np.asarray(a, rounded_dtype).astype(np.float64) for a in w.B0[pi]]
+        n = 0
+        while True:
+            if w.sources:
+                J, ro, rn = w.schedule[pi].sources(0, dtype=rounded_dtype)
+                J = [np.asarray(a, np.float64) for a in J]
+                ro, rn = np.asarray(ro, np.float64), np.asarray(rn, np.float64)
+            else:
+                J = ro = rn = None
+            E, B = oracle.psatd_step(E, B, J, ro, rn, d=p.d, dt=p.dt, workers=workers)
+            n += 1
+            cells += p.cells
+            if pi == 0 and n == 1:
+                first = (E, B)
+            if time.perf_counter() - t0 > budget_s or n >= 1000:
+                break
+            if len(w.patches) > 1 and n >= 1:
+                break
+        steps_done = max(steps_done, n)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return cells / el, el, workers, steps_done, first
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1608_05739_amd as pk
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    index = args.workload
+    default_steps = {0: 100, 1: 1000, 2: 200, 3: 500, 4: 100}[index]
+    steps = args.steps if args.steps is not None else default_steps
+    w = build_inputs(index, steps)
+    mode = "rho" if w.sources else "vacuum"
+    vacuum_batch = not w.sources
+    cells = w.cells
+
+    # ------------------------------------------------ FP32 storage, fused path
+    plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", graph=True)
+    log("[bench] fp32 fused plan:\n" + plan.info)
+    E, B, J, ro, rn = device_fields(w, plan, np.float32)
+    # one-step parity spot check on the same inputs (before timing mutates E, B)
+    E1 = [t.clone() for t in E]
+    B1 = [t.clone() for t in B]
+    plan.push(E1, B1, J, ro, rn, steps=1)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {steps} fp32 steps (+{args.warmup} warmup) ...")
+    sec = time_steps(plan, E, B, J, ro, rn, steps, args.warmup, vacuum_batch)
+    ms_step = 1e3 * sec / steps
+    value = cells * steps / sec
+    log(f"[bench]   {ms_step:.4f} ms/step, {value:.4e} cell-steps/s")
+    prof_steps = min(steps, 200)
+    pass_ms = plan.push_profiled(E, B, J, ro, rn, steps=prof_steps) if not vacuum_batch else \
+        plan.push_profiled(E, B, steps=prof_steps)
+    names, pbytes = plan.pass_names, plan.pass_bytes
+    passes = {n: {"ms": round(m, 5), "model_GBps": round(b / (m * 1e-3) / 1e9, 1),
+                  "model_bytes": b} for n, m, b in zip(names, pass_ms, pbytes)}
+    dom = int(np.argmax(pass_ms))
+    achieved = pbytes[dom] / (pass_ms[dom] * 1e-3) / 1e9
+    step_bytes = sum(pbytes)
+    log(f"[bench]   passes: {passes}")
+    traffic = measured_traffic(w.name, names[dom])
+
+    # ------------------------------------------------ FP64 storage, plain path
+    plan64 = pk.Plan(w.patches, precision="fp64", source_mode=mode, path="plain", graph=True)
+    E64, B64, J64, ro64, rn64 = device_fields(w, plan64, np.float64)
+    E64_1 = [t.clone() for t in E64]
+    B64_1 = [t.clone() for t in B64]
+    plan64.push(E64_1, B64_1, J64, ro64, rn64, steps=1)
+    torch.cuda.synchronize()
+    s64 = min(steps, args.fp64_steps)
+    log(f"[bench] timing {s64} fp64 plain steps ...")
+    sec64 = time_steps(plan64, E64, B64, J64, ro64, rn64, s64, min(args.warmup, 5), vacuum_batch)
+    pass64 = plan64.push_profiled(E64, B64, J64, ro64, rn64, steps=min(s64, 20)) if not vacuum_batch \
+        else plan64.push_profiled(E64, B64, steps=min(s64, 20))
+    fp64 = {"value": cells * s64 / sec64, "unit": "cell-steps/s", "ms_per_step": 1e3 * sec64 / s64,
+            "steps": s64, "passes": {n: round(m, 5) for n, m in zip(plan64.pass_names, pass64)},
+            "model_GBps": sum(plan64.pass_bytes) / (sec64 / s64) / 1e9}
+    log(f"[bench]   fp64 plain: {fp64['ms_per_step']:.4f} ms/step")
+
+    # ------------------------------------------------ oracle: CPU baseline + parity
+    cpu = None
+    parity = {}
+    if not args.no_cpu_baseline:
+        log(f"[bench] oracle on host cores (~{args.cpu_budget:.0f} s budget) ...")
+        v, el, workers, nst, first = cpu_baseline(w, args.cpu_budget, np.float32)
+        sample = (f"{w.name}: first {nst} step(s) of patch 0" if len(w.patches) == 1 else
+                  f"{w.name}: 1 step of the first patches within the budget")
+        cpu = {"value": v, "unit": "cell-steps/s", "cores": workers, "kind": "oracle",
+               "sample": sample + f", {el:.1f} s, scipy.fft FP64 + numpy update"}
+        if first is not None:
+            p0 = w.patches[0]
+
+            def rel(gpuE, gpuB, plan_):
+                got = [t.detach().cpu().numpy().astype(np.float64)[:p0.cells].reshape(p0.shape)
+                       for t in gpuE + gpuB]
+                ref = first[0] + first[1]
+                return float(np.sqrt(sum(np.sum((g - r) ** 2) for g, r in zip(got, ref))
+                                     / sum(np.sum(r * r) for r in ref)))
+            parity["fp32_fused_1step_rel_l2"] = rel(E1, B1, plan)
+        log(f"[bench]   cpu {v:.4e} cell-steps/s on {workers} threads; parity {parity}")
+
+    cfg = {"workload": w.name, "cells": cells, "patches": len(w.patches), "steps_per_config": default_steps,
+           "source_form": mode, "storage": "f32", "arithmetic": "f64", "path": "fused",
+           "graph": True}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded laser + harmonic comb, current sheet with continuity-consistent rho)",
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": names[dom]},
+        "step_model_GBps": step_bytes / (ms_step * 1e-3) / 1e9,
+        "step_model_frac": step_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "passes": passes,
+        "fp64_plain": fp64,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    plan64.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -9,7 +9,21 @@ fields stay real.
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def _fftn(a):
+    return sfft.fftn(a, workers=_WORKERS)
+
+
+def _ifftn(a):
+    return sfft.ifftn(a, workers=_WORKERS)
+
 
 LAMBDA0 = 1.0
 C_LIGHT = 1.0
@@ -45,28 +59,28 @@ def _kgrid(shape, d):
 
 def spectral_grad(f, d):
     """(d/dx, d/dy, d/dz) of a real periodic array, evaluated spectrally."""
-    fh = np.fft.fftn(f)
-    return tuple(np.real(np.fft.ifftn(1j * k * fh)) for k in _kgrid(f.shape, d))
+    fh = _fftn(f)
+    return tuple(np.real(_ifftn(1j * k * fh)) for k in _kgrid(f.shape, d))
 
 
 def spectral_div(F, d):
     """div of a real periodic vector field (3 arrays), evaluated spectrally."""
     kx, ky, kz = _kgrid(F[0].shape, d)
-    acc = 1j * (kx * np.fft.fftn(F[0]) + ky * np.fft.fftn(F[1]) + kz * np.fft.fftn(F[2]))
-    return np.real(np.fft.ifftn(acc))
+    acc = 1j * (kx * _fftn(F[0]) + ky * _fftn(F[1]) + kz * _fftn(F[2]))
+    return np.real(_ifftn(acc))
 
 
 def project_transverse(F, d):
     """Remove the longitudinal (curl-free) part of a vector field; the mean is kept."""
     kx, ky, kz = _kgrid(F[0].shape, d)
-    Fh = [np.fft.fftn(f) for f in F]
+    Fh = [_fftn(f) for f in F]
     k2 = kx * kx + ky * ky + kz * kz
     inv = np.zeros_like(k2)
     np.divide(1.0, k2, out=inv, where=k2 > 0)
     kdot = (kx * Fh[0] + ky * Fh[1] + kz * Fh[2]) * inv
     out = []
     for f, k in zip(Fh, (kx, ky, kz)):
-        out.append(np.real(np.fft.ifftn(f - k * kdot)))
+        out.append(np.real(_ifftn(f - k * kdot)))
     return out
 
 

@@ -690,7 +690,7 @@ static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int
                               void* hip_stream, double* ms_per_pass, int32_t max_pass) {
   if (!plan) return fail(PSATD_ERR_INVALID_ARG, "plan is NULL");
   if (nsteps < 0) return fail(PSATD_ERR_INVALID_ARG, "nsteps must be >= 0");
-  if (nsteps > 1 && plan->cfg.source_mode != PSATD_VACUUM)
+  if (nsteps > 1 && plan->cfg.source_mode != PSATD_VACUUM && !ms_per_pass)
     return fail(PSATD_ERR_INVALID_ARG, "with sources, push one step at a time (nsteps = 1)");
   if (!plan->ws) return fail(PSATD_ERR_WORKSPACE, "no workspace: call psatd_set_workspace");
   FieldPtrs fp;
