@@ -67,6 +67,7 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
 #define PSATD_FLAG_AUTOTUNE 0x1u /* time candidate launch shapes at plan time, keep the fastest */
 #define PSATD_FLAG_GRAPH 0x2u    /* replay a captured hipGraph of one step inside psatd_push   */
 #define PSATD_FLAG_NO_WORKSPACE 0x4u /* allocate no workspace: call psatd_set_workspace first */
+#define PSATD_FLAG_GENERIC_KERNELS 0x8u /* never pick shape-specialized kernels (cross-checks) */
 
 typedef struct {
   int32_t ndim;  /* 2: (x, z) plane, n[1] must be 1;  3: (x, y, z)                   */

@@ -27,6 +27,7 @@ PATH = {"fused": 0, "plain": 1}
 FLAG_AUTOTUNE = 0x1
 FLAG_GRAPH = 0x2
 FLAG_NO_WORKSPACE = 0x4
+FLAG_GENERIC_KERNELS = 0x8
 
 EXPORTED_SYMBOLS = (
     "psatd_plan", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
@@ -144,7 +145,7 @@ class Plan:
 
     def __init__(self, patches: Sequence, *, precision="fp32", source_mode="vacuum",
                  path="fused", order=0, c=1.0, eps0=1.0, autotune=False, graph=False,
-                 device=0, allocate_workspace=True):
+                 device=0, allocate_workspace=True, generic_kernels=False):
         self._lib = load_library()
         self._plan = None
         ps = [as_patch(p) for p in patches]
@@ -177,7 +178,8 @@ class Plan:
         cfg.c = float(c)
         cfg.eps0 = float(eps0)
         cfg.flags = ((FLAG_AUTOTUNE if autotune else 0) | (FLAG_GRAPH if graph else 0)
-                     | (0 if allocate_workspace else FLAG_NO_WORKSPACE))
+                     | (0 if allocate_workspace else FLAG_NO_WORKSPACE)
+                     | (FLAG_GENERIC_KERNELS if generic_kernels else 0))
         handle = ctypes.c_void_p()
         _check(self._lib, self._lib.psatd_plan(ctypes.byref(cfg), descs, len(ps), int(device),
                                                 ctypes.byref(handle)))

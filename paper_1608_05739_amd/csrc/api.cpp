@@ -11,9 +11,11 @@
 #include <string>
 #include <vector>
 
+#include "fast2d.hpp"
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "psatd.h"
+#include "update.hpp"
 
 using namespace psatd;
 
@@ -91,7 +93,7 @@ struct DeviceGuard {
   }
 };
 
-enum PassType { kLine = 0, kFused = 1, kUpdate = 2 };
+enum PassType { kLine = 0, kFused = 1, kUpdate = 2, kFastXFwd = 3, kFastZ = 4, kFastXInv = 5 };
 
 struct Pass {
   PassType type;
@@ -179,7 +181,8 @@ psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, 
   if (!(cfg->c > 0.0) || !std::isfinite(cfg->c)) return fail(PSATD_ERR_INVALID_ARG, "c must be > 0");
   if (!(cfg->eps0 > 0.0) || !std::isfinite(cfg->eps0))
     return fail(PSATD_ERR_INVALID_ARG, "eps0 must be > 0");
-  if (cfg->flags & ~(PSATD_FLAG_AUTOTUNE | PSATD_FLAG_GRAPH | PSATD_FLAG_NO_WORKSPACE))
+  if (cfg->flags & ~(PSATD_FLAG_AUTOTUNE | PSATD_FLAG_GRAPH | PSATD_FLAG_NO_WORKSPACE |
+                     PSATD_FLAG_GENERIC_KERNELS))
     return fail(PSATD_ERR_INVALID_ARG, "unknown flag bits");
   const int ndim = patches[0].ndim;
   std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -355,6 +358,18 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
     if (w.patch < 0 || w.patch >= static_cast<int>(plan->host_patches.size()))
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad patch index");
     const PatchDev& P = plan->host_patches[w.patch];
+    if (ps.type == kFastXFwd || ps.type == kFastXInv || ps.type == kFastZ) {
+      if (P.nx != fast2d::kNX || P.nz != fast2d::kNZfast || P.ndim != 2)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": patch shape not specialized");
+      const int lim = ps.type == kFastZ ? P.mx : fast2d::kTilesZ;
+      if (w.first < 0 || w.first >= lim || w.count != 1)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item out of range");
+      if (ps.type != kFastZ && (w.comp < 0 || w.comp >= plan->nin))
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad component");
+      if (ps.shape.block != fast2d::kBlock)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad block size");
+      continue;
+    }
     if (w.count < 1 || w.first < 0) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": empty item");
     if (ps.type == kUpdate) {
       if (static_cast<long long>(w.first) + w.count > P.comp_stride)
@@ -396,6 +411,47 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
   return PSATD_OK;
 }
 
+// Shape-specialized 2D passes (fast2d.hip): every patch nx = nz = 4096,
+// FP32 storage, fused path.
+bool fast2d_eligible(const psatd_plan_s* plan) {
+  const psatd_config& c = plan->cfg;
+  if (c.flags & PSATD_FLAG_GENERIC_KERNELS) return false;
+  if (plan->ndim != 2 || c.precision != PSATD_FP32 || c.path != PSATD_PATH_FUSED) return false;
+  for (const PatchDev& P : plan->host_patches)
+    if (P.nx != fast2d::kNX || P.nz != fast2d::kNZfast) return false;
+  return true;
+}
+
+Pass make_fast_pass(PassType type, const psatd_plan_s* plan, const std::vector<int>& comps,
+                    std::vector<WorkItem>& items) {
+  Pass ps;
+  ps.type = type;
+  ps.line_kind = -1;
+  ps.name = type == kFastXFwd ? "x_r2c_fwd" : (type == kFastXInv ? "x_c2r_inv" : "z_fused");
+  const size_t first = items.size();
+  double bytes = 0.0;
+  for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+    const PatchDev& P = plan->host_patches[pi];
+    const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+    if (type == kFastZ) {
+      for (int kx = 0; kx < P.mx; ++kx) items.push_back(WorkItem{static_cast<int>(pi), kx, 1, -1});
+      bytes += (plan->nin + 6) * cells * plan->elem;
+    } else {
+      for (int c : comps)
+        for (int z1 = 0; z1 < fast2d::kTilesZ; ++z1)
+          items.push_back(WorkItem{static_cast<int>(pi), z1, 1, c});
+      bytes += comps.size() * 2.0 * cells * plan->elem;
+    }
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  const size_t lds = type == kFastZ ? fast2d::z_lds_bytes() : fast2d::x_lds_bytes();
+  ps.shape = LaunchShape{ps.nitems, fast2d::kBlock, lds};
+  ps.bytes = bytes;
+  ps.mpt = type == kFastZ ? 8 : 0;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);
+  return ps;
+}
+
 psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldPtrs& f,
                           hipStream_t s) {
   hipError_t e;
@@ -409,9 +465,19 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
       e = launch_fused_z(plan->cfg.precision, plan->ndim, plan->cfg.source_mode, ps.mpt, ps.shape,
                          s, plan->d_patches, ps.d_items, ps.nitems, plan->ws, ph);
       break;
-    default:
+    case kUpdate:
       e = launch_update(plan->cfg.precision, plan->cfg.source_mode, ps.shape, s, plan->d_patches,
                         ps.d_items, ps.nitems, plan->ws, ph);
+      break;
+    case kFastXFwd:
+      e = fast2d::launch_x_fwd(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
+      break;
+    case kFastXInv:
+      e = fast2d::launch_x_inv(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
+      break;
+    default:
+      e = fast2d::launch_z_fused(plan->cfg.source_mode, ps.shape, s, plan->d_patches, ps.d_items,
+                                 ps.nitems, plan->ws, ph);
       break;
   }
   if (e != hipSuccess) return hip_fail(e, ps.name);
@@ -491,6 +557,25 @@ psatd_status build_plan(psatd_plan_s* plan) {
   }
   std::vector<double> fw;
   if (cfg.order > 0) fw = fornberg_staggered(cfg.order);
+  // The device sincos is accurate for |theta/2| <= kSincosMax; bound |k| per
+  // axis by pi/d (exact k) or (2/d) sum |C_l| (order p).
+  {
+    double wsum = 0.0;
+    for (double x : fw) wsum += std::fabs(x);
+    const double per = cfg.order > 0 ? 2.0 * wsum : M_PI;
+    for (const psatd_patch_desc& d : plan->desc) {
+      double k2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (plan->ndim == 2 && a == 1) continue;
+        const double k = per / d.d[a];
+        k2 += k * k;
+      }
+      if (0.5 * cfg.c * d.dt * std::sqrt(k2) > kSincosMax)
+        return fail(PSATD_ERR_INVALID_ARG,
+                    "c |k|max dt / 2 exceeds " + std::to_string(kSincosMax) +
+                        " (time step too large for the coefficient evaluation)");
+    }
+  }
   const size_t fw_off = take(sizeof(double) * std::max<size_t>(1, fw.size()));
 
   hipError_t e = hipMalloc(&plan->d_tables, tb);
@@ -568,7 +653,12 @@ psatd_status build_plan(psatd_plan_s* plan) {
   for (int c = 0; c < 6; ++c) out_comps.push_back(c);
   std::vector<WorkItem> items;
   plan->passes.clear();
-  plan->passes.push_back(make_line_pass(kXFwd, plan, in_comps, items));
+  if (fast2d_eligible(plan)) {
+    plan->passes.push_back(make_fast_pass(kFastXFwd, plan, in_comps, items));
+    plan->passes.push_back(make_fast_pass(kFastZ, plan, in_comps, items));
+    plan->passes.push_back(make_fast_pass(kFastXInv, plan, out_comps, items));
+  } else {
+    plan->passes.push_back(make_line_pass(kXFwd, plan, in_comps, items));
   if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYFwd, plan, in_comps, items));
   if (cfg.path == PSATD_PATH_FUSED) {
     Pass fz;
@@ -582,6 +672,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
   }
   if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYInv, plan, out_comps, items));
   plan->passes.push_back(make_line_pass(kXInv, plan, out_comps, items));
+  }
 
   for (const Pass& ps : plan->passes) {
     psatd_status st = verify_pass(plan, ps, items.data() + reinterpret_cast<size_t>(ps.d_items));
@@ -638,6 +729,7 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
     static bool attrs = false;
     if (!attrs) {
       hipError_t e = configure_kernel_attributes();
+      if (e == hipSuccess) e = fast2d::configure_attributes();
       if (e != hipSuccess) return hip_fail(e, "kernel attributes");
       attrs = true;
     }

@@ -11,6 +11,7 @@
 
 #include "fft.hpp"
 #include "kernels.hpp"
+#include "groups.hpp"
 #include "update.hpp"
 
 namespace psatd {
@@ -211,37 +212,7 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
 }
 
 // ------------------------------------------------------------------ fused z pass
-// Input and output component groups.  In 2D (k_y = 0) the update splits into
-// the s-polarized set (Ey, Bx, Bz; Jy) and the p-polarized set (Ex, Ez, By;
-// Jx, Jz, rho), processed one after the other to halve the register state.
-template <int G, int SRC>
-struct Group;
-
-// 2D s-polarization
-template <int SRC>
-struct Group<0, SRC> {
-  static constexpr int nin = (SRC == kVacuum) ? 3 : 4;
-  static constexpr int in[4] = {kEy, kBx, kBz, kJy};
-  static constexpr int nout = 3;
-  static constexpr int out_slot[3] = {0, 1, 2};
-};
-// 2D p-polarization
-template <int SRC>
-struct Group<1, SRC> {
-  static constexpr int nin = (SRC == kVacuum) ? 3 : (SRC == kJForm ? 5 : 7);
-  static constexpr int in[7] = {kEx, kEz, kBy, kJx, kJz, kRhoOld, kRhoNew};
-  static constexpr int nout = 3;
-  static constexpr int out_slot[3] = {0, 1, 2};
-};
-// 3D: everything couples
-template <int SRC>
-struct Group<2, SRC> {
-  static constexpr int nin = (SRC == kVacuum) ? 6 : (SRC == kJForm ? 9 : 11);
-  static constexpr int in[11] = {kEx, kEy, kEz, kBx, kBy, kBz, kJx, kJy, kJz, kRhoOld, kRhoNew};
-  static constexpr int nout = 6;
-  static constexpr int out_slot[6] = {0, 1, 2, 3, 4, 5};
-};
-
+// (component groups: groups.hpp)
 template <typename S, int G, int SRC, int MPT>
 __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& wi, S* ws,
                                             const Physics& ph, double2* lds) {

@@ -25,34 +25,94 @@ namespace psatd {
 
 struct Coef {
   double C, S, X1, X2, X3;
+  double Se;  // S / eps0
 };
 
-__device__ __forceinline__ double g_of_theta(double th, double sinc_th) {
-  if (th < 0.25) {
-    const double t2 = th * th;
-    return 1.0 / 6.0 -
-           t2 * (1.0 / 120.0 -
-                 t2 * (1.0 / 5040.0 -
-                       t2 * (1.0 / 362880.0 - t2 * (1.0 / 39916800.0 - t2 / 6227020800.0))));
-  }
-  return (1.0 - sinc_th) / (th * th);
+// sin and cos of a bounded argument, |h| <= kSincosMax.  Cody-Waite reduction
+// h = n pi/2 + r with pi/2 split into three parts (the first two with 33
+// significant bits, so n * part is exact for |n| < 2^20), then the Taylor
+// series of sin to r^17 and of cos to r^18 on |r| <= pi/4 (truncation below
+// 1e-18 relative).  Written with explicit fma so host and device round alike.
+constexpr double kSincosMax = 1.0e5;
+
+// Polynomial constants live in a constant-memory table so that, inside
+// persistent loops, they stay in scalar registers instead of being hoisted
+// into vector registers.
+struct TrigConsts {
+  double two_over_pi, p1, p2, p3;
+  double s[8];  // 1/17!, -1/15!, ..., -1/3!   (Horner order)
+  double c[9];  // -1/18!, 1/16!, ..., -1/2!
+  double g[6];  // 1/6, 1/120, 1/5040, 1/362880, 1/39916800, 1/6227020800
+};
+
+#define PSATD_TRIG_CONSTS                                                                      \
+  {0.63661977236758138, 1.5707963267341256, 6.077100506303966e-11, 2.0222662487959506e-21,     \
+   {2.8114572543455206e-15, -7.647163731819816e-13, 1.6059043836821613e-10,                    \
+    -2.505210838544172e-08, 2.7557319223985893e-06, -1.984126984126984e-04,                    \
+    8.333333333333333e-03, -1.6666666666666666e-01},                                           \
+   {-1.5619206968586225e-16, 4.779477332387385e-14, -1.1470745597729725e-11,                   \
+    2.08767569878681e-09, -2.755731922398589e-07, 2.48015873015873e-05, -1.388888888888889e-03, \
+    4.1666666666666664e-02, -0.5},                                                             \
+   {1.0 / 6.0, 1.0 / 120.0, 1.0 / 5040.0, 1.0 / 362880.0, 1.0 / 39916800.0, 1.0 / 6227020800.0}}
+
+__constant__ static const TrigConsts kTrigDev = PSATD_TRIG_CONSTS;
+static const TrigConsts kTrigHost = PSATD_TRIG_CONSTS;
+
+__host__ __device__ inline const TrigConsts& trig_consts() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return kTrigDev;
+#else
+  return kTrigHost;
+#endif
 }
 
-__device__ __forceinline__ Coef psatd_coef(double K, double dt, double c, double eps0,
+__host__ __device__ inline void psatd_sincos(double h, double* s_out, double* c_out) {
+  const TrigConsts& T = trig_consts();
+  const double n = rint(h * T.two_over_pi);
+  double r = fma(-n, T.p1, h);
+  r = fma(-n, T.p2, r);
+  r = fma(-n, T.p3, r);
+  const double r2 = r * r;
+  double ps = T.s[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) ps = fma(ps, r2, T.s[i]);
+  const double sr = fma(r * r2, ps, r);
+  double pc = T.c[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) pc = fma(pc, r2, T.c[i]);
+  const double cr = fma(r2, pc, 1.0);
+  const int quad = static_cast<int>(n) & 3;
+  const double sv = (quad & 1) ? cr : sr;
+  const double cv = (quad & 1) ? sr : cr;
+  *s_out = (quad & 2) ? -sv : sv;
+  *c_out = ((quad + 1) & 2) ? -cv : cv;
+}
+
+__host__ __device__ inline Coef psatd_coef(double K, double dt, double c, double eps0,
                                            double scale) {
   const double th = c * K * dt;
   const double h = 0.5 * th;
   double sh, ch;
-  sincos(h, &sh, &ch);
-  const double sinc_h = (h > 0.0) ? sh / h : 1.0;
+  psatd_sincos(h, &sh, &ch);
+  const double ih = (h > 0.0) ? 1.0 / h : 0.0;
+  const double sinc_h = (h > 0.0) ? sh * ih : 1.0;
   const double sinc_th = sinc_h * ch;  // sin(th)/th = (2 sh ch)/(2 h)
-  const double g = g_of_theta(th, sinc_th);
+  double g;
+  if (th < 0.25) {
+    const TrigConsts& T = trig_consts();
+    const double t2 = th * th;
+    g = T.g[0] - t2 * (T.g[1] - t2 * (T.g[2] - t2 * (T.g[3] - t2 * (T.g[4] - t2 * T.g[5]))));
+  } else {
+    g = (1.0 - sinc_th) * (0.25 * ih * ih);  // (1 - sinc th) / th^2
+  }
+  const double ie = scale / eps0;
   Coef k;
   k.C = (ch - sh) * (ch + sh) * scale;
   k.S = dt * sinc_th * scale;
-  k.X1 = dt * dt * sinc_h * sinc_h / (2.0 * eps0) * scale;
-  k.X2 = c * c * dt * dt * g / eps0 * scale;
-  k.X3 = c * c * dt * dt * (g - 0.5 * sinc_h * sinc_h) / eps0 * scale;
+  k.Se = dt * sinc_th * ie;
+  k.X1 = dt * dt * sinc_h * sinc_h * 0.5 * ie;
+  k.X2 = c * c * dt * dt * g * ie;
+  k.X3 = c * c * dt * dt * (g - 0.5 * sinc_h * sinc_h) * ie;
   return k;
 }
 
@@ -112,6 +172,185 @@ __device__ __forceinline__ void update_mode(const double kx, const double ky, co
       for (int i = 0; i < 3; ++i) Eo[i] = cadd(Eo[i], i_times(lam, kv[i]));
     }
   }
+}
+
+// ------------------------------------------------------------------ 2D forms
+// In 2D (k_y = 0) the update splits into two independent sets:
+//   s-polarization (Ey, Bx, Bz; Jy):
+//     Ey' = C Ey + i c^2 S (kz Bx - kx Bz) - (S/eps0) Jy
+//     Bx' = C Bx + i S kz Ey - i X1 kz Jy
+//     Bz' = C Bz - i S kx Ey + i X1 kx Jy
+//   p-polarization (Ex, Ez, By; Jx, Jz, rho):
+//     Ex' = C Ex - i c^2 S kz By - (S/eps0) Jx + [longitudinal]_x
+//     Ez' = C Ez + i c^2 S kx By - (S/eps0) Jz + [longitudinal]_z
+//     By' = C By - i S (kz Ex - kx Ez) + i X1 (kz Jx - kx Jz)
+//   [longitudinal] = i k (X3 rho_old - X2 rho_new)                       (rho form)
+//                  = eps0 c^2 X1 k (k.E) - dt X2 k (k.J)                 (J form)
+// These are the general update with k_y = 0 written out, so that no term is
+// multiplied by an explicit zero.
+__device__ __forceinline__ double2 ld2(const float2& v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ float2 st2(double2 v) {
+  return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+__device__ __forceinline__ double2 ld2(const double2& v) { return v; }
+template <typename V>
+__device__ __forceinline__ V st2t(double2 v);
+template <>
+__device__ __forceinline__ float2 st2t<float2>(double2 v) { return st2(v); }
+template <>
+__device__ __forceinline__ double2 st2t<double2>(double2 v) { return v; }
+
+// in/out: Ey, Bx, Bz (updated in place), Jy (read, sources only)
+template <int SRC, typename V>
+__device__ __forceinline__ void update_2d_s(double kx, double kz, const Coef& q, double c,
+                                            double eps0, V& Ey, V& Bx, V& Bz, const V Jy) {
+  const double2 ey = ld2(Ey), bx = ld2(Bx), bz = ld2(Bz);
+  const double cS = c * c * q.S;
+  const double2 kb = make_double2(kz * bx.x - kx * bz.x, kz * bx.y - kx * bz.y);
+  double2 ey2 = make_double2(q.C * ey.x - cS * kb.y, q.C * ey.y + cS * kb.x);
+  double2 bx2 = make_double2(q.C * bx.x - q.S * kz * ey.y, q.C * bx.y + q.S * kz * ey.x);
+  double2 bz2 = make_double2(q.C * bz.x + q.S * kx * ey.y, q.C * bz.y - q.S * kx * ey.x);
+  if constexpr (SRC != kVacuum) {
+    const double2 jy = ld2(Jy);
+    const double sj = q.S / eps0;
+    ey2.x -= sj * jy.x;
+    ey2.y -= sj * jy.y;
+    bx2.x += q.X1 * kz * jy.y;
+    bx2.y -= q.X1 * kz * jy.x;
+    bz2.x -= q.X1 * kx * jy.y;
+    bz2.y += q.X1 * kx * jy.x;
+  }
+  Ey = st2t<V>(ey2);
+  Bx = st2t<V>(bx2);
+  Bz = st2t<V>(bz2);
+}
+
+// in/out: Ex, Ez, By (updated in place); Jx, Jz, rho_old, rho_new (read)
+template <int SRC, typename V>
+__device__ __forceinline__ void update_2d_p(double kx, double kz, const Coef& q, double c,
+                                            double eps0, double dt, V& Ex, V& Ez, V& By,
+                                            const V Jx, const V Jz, const V ro, const V rn) {
+  const double2 ex = ld2(Ex), ez = ld2(Ez), by = ld2(By);
+  const double cS = c * c * q.S;
+  // E' = C E + i c^2 S (k x B): (k x B)_x = -kz By, (k x B)_z = kx By
+  double2 ex2 = make_double2(q.C * ex.x + cS * kz * by.y, q.C * ex.y - cS * kz * by.x);
+  double2 ez2 = make_double2(q.C * ez.x - cS * kx * by.y, q.C * ez.y + cS * kx * by.x);
+  // B' = C B - i S (k x E)_y, (k x E)_y = kz Ex - kx Ez
+  const double2 ke = make_double2(kz * ex.x - kx * ez.x, kz * ex.y - kx * ez.y);
+  double2 by2 = make_double2(q.C * by.x + q.S * ke.y, q.C * by.y - q.S * ke.x);
+  if constexpr (SRC == kJForm) {
+    const double a = eps0 * c * c * q.X1;
+    const double2 kdE = make_double2(kx * ex.x + kz * ez.x, kx * ex.y + kz * ez.y);
+    ex2.x += a * kx * kdE.x;
+    ex2.y += a * kx * kdE.y;
+    ez2.x += a * kz * kdE.x;
+    ez2.y += a * kz * kdE.y;
+  }
+  if constexpr (SRC != kVacuum) {
+    const double2 jx = ld2(Jx), jz = ld2(Jz);
+    const double sj = q.S / eps0;
+    ex2.x -= sj * jx.x;
+    ex2.y -= sj * jx.y;
+    ez2.x -= sj * jz.x;
+    ez2.y -= sj * jz.y;
+    // + i X1 (kz Jx - kx Jz)
+    const double2 kj = make_double2(kz * jx.x - kx * jz.x, kz * jx.y - kx * jz.y);
+    by2.x -= q.X1 * kj.y;
+    by2.y += q.X1 * kj.x;
+    if constexpr (SRC == kJForm) {
+      const double b = dt * q.X2;
+      const double2 kdJ = make_double2(kx * jx.x + kz * jz.x, kx * jx.y + kz * jz.y);
+      ex2.x -= b * kx * kdJ.x;
+      ex2.y -= b * kx * kdJ.y;
+      ez2.x -= b * kz * kdJ.x;
+      ez2.y -= b * kz * kdJ.y;
+    } else {
+      const double2 r0 = ld2(ro), r1 = ld2(rn);
+      const double2 lam = make_double2(q.X3 * r0.x - q.X2 * r1.x, q.X3 * r0.y - q.X2 * r1.y);
+      // + i k lam
+      ex2.x -= kx * lam.y;
+      ex2.y += kx * lam.x;
+      ez2.x -= kz * lam.y;
+      ez2.y += kz * lam.x;
+    }
+  }
+  Ex = st2t<V>(ex2);
+  Ez = st2t<V>(ez2);
+  By = st2t<V>(by2);
+}
+
+// ------------------------------------------------------------------ 2D, phased
+// The same 2D update split into a source part, evaluated once the sources are
+// transformed, and a field part.  The source part returns the contributions
+//   s-pol: sEy = -(S/eps0) Jy,  sBx = -i X1 kz Jy,  sBz = i X1 kx Jy
+//   p-pol: sEx = -(S/eps0) Jx + Lx,  sEz = -(S/eps0) Jz + Lz,  sBy = i X1 (kz Jx - kx Jz)
+//          L = i k (X3 rho_old - X2 rho_new)      (rho form)
+//          L = -dt X2 k (k.J)                      (J form)
+// and the field part adds them to C E + i c^2 S (k x B) [+ eps0 c^2 X1 k (k.E),
+// J form] and C B - i S (k x E).
+__device__ __forceinline__ void src_2d_s(double kx, double kz, const Coef& q, double2 jy,
+                                         double2& sEy, double2& sBx, double2& sBz) {
+  sEy = make_double2(-q.Se * jy.x, -q.Se * jy.y);
+  sBx = make_double2(q.X1 * kz * jy.y, -q.X1 * kz * jy.x);
+  sBz = make_double2(-q.X1 * kx * jy.y, q.X1 * kx * jy.x);
+}
+
+template <int SRC>
+__device__ __forceinline__ void src_2d_p(double kx, double kz, const Coef& q, double dt,
+                                         double2 jx, double2 jz, double2 ro, double2 rn,
+                                         double2& sEx, double2& sEz, double2& sBy) {
+  sEx = make_double2(-q.Se * jx.x, -q.Se * jx.y);
+  sEz = make_double2(-q.Se * jz.x, -q.Se * jz.y);
+  const double2 kj = make_double2(kz * jx.x - kx * jz.x, kz * jx.y - kx * jz.y);
+  sBy = make_double2(-q.X1 * kj.y, q.X1 * kj.x);
+  if constexpr (SRC == kJForm) {
+    const double b = dt * q.X2;
+    const double2 kdJ = make_double2(kx * jx.x + kz * jz.x, kx * jx.y + kz * jz.y);
+    sEx.x -= b * kx * kdJ.x;
+    sEx.y -= b * kx * kdJ.y;
+    sEz.x -= b * kz * kdJ.x;
+    sEz.y -= b * kz * kdJ.y;
+  } else {
+    const double2 lam = make_double2(q.X3 * ro.x - q.X2 * rn.x, q.X3 * ro.y - q.X2 * rn.y);
+    sEx.x -= kx * lam.y;
+    sEx.y += kx * lam.x;
+    sEz.x -= kz * lam.y;
+    sEz.y += kz * lam.x;
+  }
+}
+
+// s-pol field part, in place; (sEy, sBx, sBz) = 0 in vacuum.
+__device__ __forceinline__ void fld_2d_s(double kx, double kz, double C, double S, double c,
+                                         double2& ey, double2& bx, double2& bz, double2 sEy,
+                                         double2 sBx, double2 sBz) {
+  const double cS = c * c * S;
+  const double2 kb = make_double2(kz * bx.x - kx * bz.x, kz * bx.y - kx * bz.y);
+  const double2 e0 = ey;
+  ey = make_double2(C * e0.x - cS * kb.y + sEy.x, C * e0.y + cS * kb.x + sEy.y);
+  bx = make_double2(C * bx.x - S * kz * e0.y + sBx.x, C * bx.y + S * kz * e0.x + sBx.y);
+  bz = make_double2(C * bz.x + S * kx * e0.y + sBz.x, C * bz.y - S * kx * e0.x + sBz.y);
+}
+
+// p-pol field part, in place.  L1 = eps0 c^2 X1 (J form only, else unused).
+template <int SRC>
+__device__ __forceinline__ void fld_2d_p(double kx, double kz, double C, double S, double L1,
+                                         double c, double2& ex, double2& ez, double2& by,
+                                         double2 sEx, double2 sEz, double2 sBy) {
+  const double cS = c * c * S;
+  const double2 ke = make_double2(kz * ex.x - kx * ez.x, kz * ex.y - kx * ez.y);
+  const double2 b0 = by;
+  double2 ex2 = make_double2(C * ex.x + cS * kz * b0.y + sEx.x, C * ex.y - cS * kz * b0.x + sEx.y);
+  double2 ez2 = make_double2(C * ez.x - cS * kx * b0.y + sEz.x, C * ez.y + cS * kx * b0.x + sEz.y);
+  if constexpr (SRC == kJForm) {
+    const double2 kdE = make_double2(kx * ex.x + kz * ez.x, kx * ex.y + kz * ez.y);
+    ex2.x += L1 * kx * kdE.x;
+    ex2.y += L1 * kx * kdE.y;
+    ez2.x += L1 * kz * kdE.x;
+    ez2.y += L1 * kz * kdE.y;
+  }
+  by = make_double2(C * b0.x + S * ke.y + sBy.x, C * b0.y - S * ke.x + sBy.y);
+  ex = ex2;
+  ez = ez2;
 }
 
 }  // namespace psatd
