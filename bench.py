@@ -146,6 +146,30 @@ def cpu_baseline(w, budget_s, rounded_dtype):
     return cells / el, el, workers, steps_done, first
 
 
+def run_fp64(pk, w, mode, cells, steps, args, vacuum_batch):
+    """The plain FP64 path on the same workload (reported beside the FP32 one)."""
+    import torch
+
+    plan64 = pk.Plan(w.patches, precision="fp64", source_mode=mode, path="plain", graph=True)
+    E64, B64, J64, ro64, rn64 = device_fields(w, plan64, np.float64)
+    E64_1 = [t.clone() for t in E64]
+    B64_1 = [t.clone() for t in B64]
+    plan64.push(E64_1, B64_1, J64, ro64, rn64, steps=1)
+    torch.cuda.synchronize()
+    s64 = min(steps, args.fp64_steps)
+    log(f"[bench] timing {s64} fp64 plain steps ...")
+    sec64 = time_steps(plan64, E64, B64, J64, ro64, rn64, s64, min(args.warmup, 5), vacuum_batch)
+    pass64 = plan64.push_profiled(E64, B64, J64, ro64, rn64, steps=min(s64, 20)) if not vacuum_batch \
+        else plan64.push_profiled(E64, B64, steps=min(s64, 20))
+    fp64 = {"value": cells * s64 / sec64, "unit": "cell-steps/s", "ms_per_step": 1e3 * sec64 / s64,
+            "steps": s64, "passes": {n: round(m, 5) for n, m in zip(plan64.pass_names, pass64)},
+            "model_GBps": sum(plan64.pass_bytes) / (sec64 / s64) / 1e9}
+    log(f"[bench]   fp64 plain: {fp64['ms_per_step']:.4f} ms/step")
+
+    plan64.close()
+    return fp64
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +179,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of "
+                         "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--skip-fp64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -166,6 +194,15 @@ def main():
     import paper_1608_05739_amd as pk
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read + written")
+        del src, dst
     index = args.workload
     default_steps = {0: 100, 1: 1000, 2: 200, 3: 500, 4: 100}[index]
     steps = args.steps if args.steps is not None else default_steps
@@ -201,21 +238,9 @@ def main():
     traffic = measured_traffic(w.name, names[dom])
 
     # ------------------------------------------------ FP64 storage, plain path
-    plan64 = pk.Plan(w.patches, precision="fp64", source_mode=mode, path="plain", graph=True)
-    E64, B64, J64, ro64, rn64 = device_fields(w, plan64, np.float64)
-    E64_1 = [t.clone() for t in E64]
-    B64_1 = [t.clone() for t in B64]
-    plan64.push(E64_1, B64_1, J64, ro64, rn64, steps=1)
-    torch.cuda.synchronize()
-    s64 = min(steps, args.fp64_steps)
-    log(f"[bench] timing {s64} fp64 plain steps ...")
-    sec64 = time_steps(plan64, E64, B64, J64, ro64, rn64, s64, min(args.warmup, 5), vacuum_batch)
-    pass64 = plan64.push_profiled(E64, B64, J64, ro64, rn64, steps=min(s64, 20)) if not vacuum_batch \
-        else plan64.push_profiled(E64, B64, steps=min(s64, 20))
-    fp64 = {"value": cells * s64 / sec64, "unit": "cell-steps/s", "ms_per_step": 1e3 * sec64 / s64,
-            "steps": s64, "passes": {n: round(m, 5) for n, m in zip(plan64.pass_names, pass64)},
-            "model_GBps": sum(plan64.pass_bytes) / (sec64 / s64) / 1e9}
-    log(f"[bench]   fp64 plain: {fp64['ms_per_step']:.4f} ms/step")
+    fp64 = None
+    if not args.skip_fp64:
+        fp64 = run_fp64(pk, w, mode, cells, steps, args, vacuum_batch)
 
     # ------------------------------------------------ oracle: CPU baseline + parity
     cpu = None
@@ -266,7 +291,6 @@ def main():
         "cpu_baseline": cpu,
     }
     plan.close()
-    plan64.close()
     print(json.dumps(out), flush=True)
 
 

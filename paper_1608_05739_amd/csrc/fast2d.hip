@@ -48,29 +48,32 @@ __device__ __forceinline__ void powers(double2 w, double2* wp) {
 }
 
 // Exchange 32 complex values through a wave region: value (b, q) is written at
-// logical index widx(b, q) and value (b', q') is read back from ridx(b', q').
+// padded index widx(b, q) and value (b', q') is read back from ridx(b', q').
+// The index functions return padx() of the logical index written as a per-lane
+// base plus a compile-time constant, so the constants fold into the LDS
+// instruction offsets instead of each index taking registers of its own.
 template <int NB_W, int NQ_W, int NB_R, int NQ_R, typename WF, typename RF>
 __device__ __forceinline__ void wave_exchange(double* region, double2 (&v)[NB_W][NQ_W],
                                               double2 (&out)[NB_R][NQ_R], WF widx, RF ridx) {
 #pragma unroll
   for (int b = 0; b < NB_W; ++b)
 #pragma unroll
-    for (int q = 0; q < NQ_W; ++q) region[padx(widx(b, q))] = v[b][q].x;
+    for (int q = 0; q < NQ_W; ++q) region[widx(b, q)] = v[b][q].x;
   wave_lds_sync();
 #pragma unroll
   for (int b = 0; b < NB_R; ++b)
 #pragma unroll
-    for (int q = 0; q < NQ_R; ++q) out[b][q].x = region[padx(ridx(b, q))];
+    for (int q = 0; q < NQ_R; ++q) out[b][q].x = region[ridx(b, q)];
   wave_lds_sync();
 #pragma unroll
   for (int b = 0; b < NB_W; ++b)
 #pragma unroll
-    for (int q = 0; q < NQ_W; ++q) region[padx(widx(b, q))] = v[b][q].y;
+    for (int q = 0; q < NQ_W; ++q) region[widx(b, q)] = v[b][q].y;
   wave_lds_sync();
 #pragma unroll
   for (int b = 0; b < NB_R; ++b)
 #pragma unroll
-    for (int q = 0; q < NQ_R; ++q) out[b][q].y = region[padx(ridx(b, q))];
+    for (int q = 0; q < NQ_R; ++q) out[b][q].y = region[ridx(b, q)];
   wave_lds_sync();
 }
 
@@ -87,8 +90,12 @@ __device__ __forceinline__ void wave_fft2048(double* region, double2 (&a)[2][16]
 #pragma unroll
   for (int b = 0; b < 2; ++b) DFT<16, SIGN>::run(a[b]);
   double2 s[2][16];
-  wave_exchange(region, a, s, [&](int b, int q) { return 16 * (l + 64 * b) + q; },
-                [&](int b, int q) { return l + 64 * b + 128 * q; });
+  // padx(16 (l + 64 b) + q) = 17 l + 1088 b + q            (q < 16)
+  // padx(l + 64 b + 128 q)   = l + (l >> 4) + 68 b + 136 q
+  const int wA = 17 * l;
+  const int rA = l + (l >> 4);
+  wave_exchange(region, a, s, [&](int b, int q) { return wA + 1088 * b + q; },
+                [&](int b, int q) { return rA + 68 * b + 136 * q; });
   // stage B: radix 16, Ns = 16, k = j mod 16 = l mod 16
   {
     double2 wq = twB;
@@ -101,10 +108,11 @@ __device__ __forceinline__ void wave_fft2048(double* region, double2 (&a)[2][16]
 #pragma unroll
     for (int b = 0; b < 2; ++b) DFT<16, SIGN>::run(s[b]);
   }
-  const int kB = l & 15;
-  wave_exchange(region, s, c,
-                [&](int b, int q) { return (l + 64 * b - kB) * 16 + kB + 16 * q; },
-                [&](int b, int q) { return l + 64 * b + 256 * q; });
+  // padx((l + 64 b - kB) 16 + kB + 16 q) = 272 (l >> 4) + kB + 1088 b + 17 q   (kB = l mod 16)
+  // padx(l + 64 b + 256 q)                = l + (l >> 4) + 68 b + 272 q
+  const int wB = 272 * (l >> 4) + (l & 15);
+  wave_exchange(region, s, c, [&](int b, int q) { return wB + 1088 * b + 17 * q; },
+                [&](int b, int q) { return rA + 68 * b + 272 * q; });
   // stage C: radix 8, Ns = 256, k = j
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -180,15 +188,12 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
       for (int r = 0; r < 8; ++r) {
         const float2* zr = reinterpret_cast<const float2*>(lds_d + r * kRegion);
         const double2 za = ld_f2(zr + kx);
-        if (kx == 0) {
-          X[r] = make_double2(za.x + za.y, za.x - za.y);
-        } else {
-          const double2 zb = ld_f2(zr + km);
-          const double2 e = make_double2(0.5 * (za.x + zb.x), 0.5 * (za.y - zb.y));
-          const double2 d = make_double2(za.x - zb.x, za.y + zb.y);
-          const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);
-          X[r] = cadd(e, cmul(wk, o));
-        }
+        const double2 zb = ld_f2(zr + km);  // km = 0 for kx = 0: in bounds, result replaced
+        const double2 e = make_double2(0.5 * (za.x + zb.x), 0.5 * (za.y - zb.y));
+        const double2 d = make_double2(za.x - zb.x, za.y + zb.y);
+        const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);
+        X[r] = cadd(e, cmul(wk, o));
+        if (kx == 0) X[r] = make_double2(za.x + za.y, za.x - za.y);
       }
       DFT<8, -1>::run(X);
       float4* dst = reinterpret_cast<float4*>(out + (long long)kx * kNZ + 8 * z1);
@@ -247,6 +252,12 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 #pragma unroll
     for (int b = 0; b < 4; ++b) twC[b] = cconj(tw2048[l + 64 * b]);
     const float2* zrow = reinterpret_cast<const float2*>(region);
+    const float2* zmir = zrow + (64 - l);
+    // pre-twiddles W^k, k = l + 64 b + 128 q: start at W^(l + 64 b), step W^128
+    double2 wk[2];
+    wk[0] = P->post[l];
+    wk[1] = P->post[l + 64];
+    const double2 wstep = P->post[128];
     double2 a[2][16];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -255,15 +266,16 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
         __builtin_amdgcn_sched_barrier(0);
         const int k = l + 64 * b + 128 * q;
         const double2 xa = ld_f2(zrow + k);
-        if (k == 0) {
-          a[b][q] = make_double2(xa.x + xa.y, xa.x - xa.y);
-        } else {
-          const double2 xb = ld_f2(zrow + (kMX - k));
-          const double2 p = make_double2(xa.x + xb.x, xa.y - xb.y);
-          const double2 m = make_double2(xa.x - xb.x, xa.y + xb.y);
-          const double2 t1 = cmul(cconj(P->post[k & (kMX - 1)]), m);
-          a[b][q] = make_double2(p.x - t1.y, p.y + t1.x);
-        }
+        // mirror index kMX - k = (64 - l) + 64 (1 - b) + 128 (15 - q), a lane base
+        // plus a constant; for k = 0 it is kMX, inside the wave's padded region,
+        // and the k = 0 entry (DC and Nyquist packed together) is selected below
+        const double2 xb = ld_f2(zmir + 64 * (1 - b) + 128 * (15 - q));
+        const double2 p = make_double2(xa.x + xb.x, xa.y - xb.y);
+        const double2 m = make_double2(xa.x - xb.x, xa.y + xb.y);
+        const double2 t1 = cmul(cconj(wk[b]), m);
+        a[b][q] = make_double2(p.x - t1.y, p.y + t1.x);
+        if (b == 0 && q == 0 && l == 0) a[b][q] = make_double2(xa.x + xa.y, xa.x - xa.y);
+        if (q < 15) wk[b] = cmul(wk[b], wstep);
       }
     wave_lds_sync();
     double2 c[4][8];
@@ -287,9 +299,12 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 // buffers laid out [e][k2] (element e of group k2 at 8 e + k2): the eight
 // lanes that the LDS serves together share j and differ in k2, so every
 // exchange is bank-conflict free.
+// The twiddle bases are read from the table inside each call, after a
+// barrier: otherwise the compiler would keep the powers of the (identical)
+// bases of every call live across the whole kernel.
 template <int SIGN>
 __device__ __forceinline__ void fft512_group(double2 (&v)[8], double2* bufA, double2* bufB, int j,
-                                             int k2, double2 w2, double2 w3) {
+                                             int k2, const double2* __restrict__ tw4096) {
   // stage 1: radix 8, Ns = 1
   DFT<8, SIGN>::run(v);
 #pragma unroll
@@ -297,13 +312,15 @@ __device__ __forceinline__ void fft512_group(double2 (&v)[8], double2* bufA, dou
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = bufA[(j + 64 * q) * 8 + k2];
-  // stage 2: radix 8, Ns = 8, k = j mod 8
+  // stage 2: radix 8, Ns = 8, k = j mod 8, w = exp(SIGN 2 pi i k / 64)
   {
-    double2 wq = w2;
-    v[1] = cmul(v[1], w2);
+    double2 w = tw4096[64 * (j & 7)];
+    if constexpr (SIGN > 0) w.y = -w.y;
+    double2 wq = w;
+    v[1] = cmul(v[1], w);
 #pragma unroll
     for (int q = 2; q < 8; ++q) {
-      wq = cmul(wq, w2);
+      wq = cmul(wq, w);
       v[q] = cmul(v[q], wq);
     }
   }
@@ -314,13 +331,15 @@ __device__ __forceinline__ void fft512_group(double2 (&v)[8], double2* bufA, dou
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = bufB[(j + 64 * q) * 8 + k2];
-  // stage 3: radix 8, Ns = 64, k = j
+  // stage 3: radix 8, Ns = 64, k = j, w = exp(SIGN 2 pi i j / 512)
   {
-    double2 wq = w3;
-    v[1] = cmul(v[1], w3);
+    double2 w = tw4096[8 * j];
+    if constexpr (SIGN > 0) w.y = -w.y;
+    double2 wq = w;
+    v[1] = cmul(v[1], w);
 #pragma unroll
     for (int q = 2; q < 8; ++q) {
-      wq = cmul(wq, w3);
+      wq = cmul(wq, w);
       v[q] = cmul(v[q], wq);
     }
   }
@@ -329,8 +348,8 @@ __device__ __forceinline__ void fft512_group(double2 (&v)[8], double2* bufA, dou
 
 // Forward transform of one component column into FP32 registers (modes t + 512 q).
 __device__ __forceinline__ void z_forward(const float2* src, float2 (&dst)[8], double2* bufA,
-                                          double2* bufB, int t, int j, int k2, double2 w2,
-                                          double2 w3) {
+                                          double2* bufB, int t, int j, int k2,
+                                          const double2* __restrict__ tw4096) {
   double2 v[8];
   // uniform base per q plus one 32-bit lane offset (SGPR-base addressing)
 #pragma unroll
@@ -338,19 +357,21 @@ __device__ __forceinline__ void z_forward(const float2* src, float2 (&dst)[8], d
     const float2* __restrict__ bq = src + 512 * q;
     v[q] = ld_f2(bq + t);
   }
-  fft512_group<-1>(v, bufA, bufB, j, k2, w2, w3);
+  fft512_group<-1>(v, bufA, bufB, j, k2, tw4096);
 #pragma unroll
   for (int q = 0; q < 8; ++q) dst[q] = st2(v[q]);
+  // keep the transform's temporaries apart from the update that follows
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Inverse transform of one component held in registers, twiddle W4096^(-z1 k2), store.
 __device__ __forceinline__ void z_inverse(const float2 (&src)[8], float2* dst, double2* bufA,
-                                          double2* bufB, int t, int j, int k2, double2 w2i,
-                                          double2 w3i, const double2* __restrict__ tw4096) {
+                                          double2* bufB, int t, int j, int k2,
+                                          const double2* __restrict__ tw4096) {
   double2 v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = ld2(src[q]);
-  fft512_group<1>(v, bufA, bufB, j, k2, w2i, w3i);
+  fft512_group<1>(v, bufA, bufB, j, k2, tw4096);
   // W4096^(-z1 k2) for z1 = j + 64 q: start at W^(-j k2), step W^(-64 k2)
   double2 tq = cconj(tw4096[(j * k2) & (kNZ - 1)]);
   const double2 step = cconj(tw4096[(64 * k2) & (kNZ - 1)]);
@@ -362,111 +383,375 @@ __device__ __forceinline__ void z_inverse(const float2 (&src)[8], float2* dst, d
   }
 }
 
-// One polarization group of one column (G = 0: s-pol, G = 1: p-pol), in three
-// phases so that at most three transformed fields, three source contributions
-// and the per-mode C and S are live at once:
-//   sources: transform J (and rho), evaluate the coefficients, fold the
-//            sources into three contributions per mode;
-//   fields:  transform E and B, apply C, S and the contributions;
-//   inverse: transform the three updated components back.
-template <int G, int SRC>
-__device__ __forceinline__ void z_group(const PatchDev* P, int kxcol, float* ws, const Physics& ph,
-                                        double2* bufA, double2* bufB, const double2& w2,
-                                        const double2& w3) {
-  constexpr bool kSrc = SRC != kVacuum;
-  constexpr int kF0 = G == 0 ? kEy : kEx;
-  constexpr int kF1 = G == 0 ? kBx : kEz;
-  constexpr int kF2 = G == 0 ? kBz : kBy;
-  const int t = threadIdx.x;
-  const int k2 = t & 7;
-  const int j = t >> 3;
-  float2* col = reinterpret_cast<float2*>(ws) + P->off_spec + (long long)kxcol * kNZ;
-  const long long cs = P->comp_stride;
-  const double kx = P->kx[kxcol];
-  const double dt = P->dt;
+// Per-column state of the z pass: thread t = 8 j + k2 holds the modes
+// kz index t + 512 q, q < 8, of column kx.
+struct ZCol {
+  float2* col;       // workspace spectrum of column kx, component 0
+  long long cs;      // component stride (complex elements)
+  double kx, dt, c, c2, eps0, ie, scale;
+  const double* kz;  // kz table
+  const double2* tw; // exp(-2 pi i m / 4096)
+  int t, j, k2;
+  double2* bufA;
+  double2* bufB;
 
-  float2 sc[3][8];  // source contributions
-  double cC[8], cS[8], cL[8];
+  // The empty asm makes every read of kz opaque to the optimizer: the
+  // coefficients are recomputed on purpose in later phases, and merging those
+  // evaluations would keep them live across the transforms in between.
+  __device__ __forceinline__ double kz_of(int q) const {
+    const double* __restrict__ kzq = kz + 512 * q;
+    double v = kzq[t];
+    asm volatile("" : "+v"(v));
+    return v;
+  }
+  __device__ __forceinline__ Coef coef(double kzv) const {
+    return psatd_coef(sqrt(kx * kx + kzv * kzv), dt, c, eps0, scale);
+  }
+  __device__ __forceinline__ void fwd(int comp, float2 (&dst)[8]) const {
+    z_forward(col + comp * cs, dst, bufA, bufB, t, j, k2, tw);
+  }
+  __device__ __forceinline__ void inv(int comp, const float2 (&src)[8]) const {
+    z_inverse(src, col + comp * cs, bufA, bufB, t, j, k2, tw);
+  }
+};
+
+__device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* ws,
+                                          const Physics& ph, double2* bufA, double2* bufB) {
+  ZCol z;
+  z.col = reinterpret_cast<float2*>(ws) + P->off_spec + (long long)kxcol * kNZ;
+  z.cs = P->comp_stride;
+  z.kx = P->kx[kxcol];
+  z.dt = P->dt;
+  z.c = ph.c;
+  z.c2 = ph.c * ph.c;
+  z.eps0 = ph.eps0;
+  z.ie = 1.0 / ph.eps0;
+  z.scale = P->inv_n;
+  z.kz = P->kz;
+  z.tw = P->fz.tw;
+  z.t = threadIdx.x;
+  z.k2 = z.t & 7;
+  z.j = z.t >> 3;
+  z.bufA = bufA;
+  z.bufB = bufB;
+  return z;
+}
+
+// The update is linear in every input, so each group accumulates its three
+// outputs while its inputs are transformed one at a time: only the FP32
+// accumulators, the per-mode coefficients that later phases need and the
+// transform in flight are live.  The arithmetic of every term is FP64.
+//
+// s-pol (Ey, Bx, Bz), any source form:
+//   sources Jy: Ey' = -(S/eps0) Jy, Bx' = -i X1 kz Jy, Bz' = i X1 kx Jy
+//   Bx: Ey' += i c^2 S kz Bx,  Bx' += C Bx
+//   Bz: Ey' -= i c^2 S kx Bz,  Bz' += C Bz
+//   Ey: Ey' += C Ey,  Bx' += i S kz Ey,  Bz' -= i S kx Ey
+// p-pol (Ex, Ez, By) in vacuum:
+//   By: Ex' -= i c^2 S kz By,  Ez' += i c^2 S kx By,  By' += C By
+//   Ex: Ex' += C Ex,  By' -= i S kz Ex
+//   Ez: Ez' += C Ez,  By' += i S kx Ez
+// (p-pol with sources: z_ppol_sources.)
+template <int G, int SRC>
+__device__ __forceinline__ void z_group(const ZCol& z) {
+  static_assert(G == 0 || SRC == kVacuum, "p-pol with sources has its own schedule");
+  constexpr bool kSrc = SRC != kVacuum;
+  constexpr int kO0 = G == 0 ? kEy : kEx;
+  constexpr int kO1 = G == 0 ? kBx : kEz;
+  constexpr int kO2 = G == 0 ? kBz : kBy;
+  const double kx = z.kx, c2 = z.c2;
+
+  float2 acc[3][8];
+  double cC[8], cS[8];
+
   if constexpr (kSrc) {
-    if constexpr (G == 0) {
-      float2 jy[8];
-      z_forward(col + kJy * cs, jy, bufA, bufB, t, j, k2, w2, w3);
+    float2 jy[8];
+    z.fwd(kJy, jy);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double* __restrict__ kzq = P->kz + 512 * q;
-        const double kz = kzq[t];
-        const Coef cf = psatd_coef(sqrt(kx * kx + kz * kz), dt, ph.c, ph.eps0, P->inv_n);
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const Coef cf = z.coef(kz);
+      cC[q] = cf.C;
+      cS[q] = cf.S;
+      double2 a, b, c;
+      src_2d_s(kx, kz, cf, ld2(jy[q]), a, b, c);
+      acc[0][q] = st2(a);
+      acc[1][q] = st2(b);
+      acc[2][q] = st2(c);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---- field 1: s-pol Bx, p-pol By
+  {
+    float2 f[8];
+    z.fwd(G == 0 ? kBx : kBy, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      if constexpr (!kSrc) {
+        const Coef cf = z.coef(kz);
         cC[q] = cf.C;
         cS[q] = cf.S;
-        double2 a, b, c;
-        src_2d_s(kx, kz, cf, ld2(jy[q]), a, b, c);
-        sc[0][q] = st2(a);
-        sc[1][q] = st2(b);
-        sc[2][q] = st2(c);
-        __builtin_amdgcn_sched_barrier(0);
       }
-    } else {
-      float2 jx[8], jz[8], ro[8], rn[8];
-      z_forward(col + kJx * cs, jx, bufA, bufB, t, j, k2, w2, w3);
-      z_forward(col + kJz * cs, jz, bufA, bufB, t, j, k2, w2, w3);
-      if constexpr (SRC == kRho) {
-        z_forward(col + kRhoOld * cs, ro, bufA, bufB, t, j, k2, w2, w3);
-        z_forward(col + kRhoNew * cs, rn, bufA, bufB, t, j, k2, w2, w3);
+      const double C = cC[q], cS2 = c2 * cS[q];
+      const double2 v = ld2(f[q]);
+      double2 a0 = kSrc ? ld2(acc[0][q]) : make_double2(0.0, 0.0);
+      double2 a1 = kSrc ? ld2(acc[1][q]) : make_double2(0.0, 0.0);
+      double2 a2 = kSrc ? ld2(acc[2][q]) : make_double2(0.0, 0.0);
+      if constexpr (G == 0) {
+        a0.x -= cS2 * kz * v.y;
+        a0.y += cS2 * kz * v.x;
+        a1.x += C * v.x;
+        a1.y += C * v.y;
+      } else {
+        a0.x += cS2 * kz * v.y;
+        a0.y -= cS2 * kz * v.x;
+        a1.x -= cS2 * kx * v.y;
+        a1.y += cS2 * kx * v.x;
+        a2.x += C * v.x;
+        a2.y += C * v.y;
       }
+      acc[0][q] = st2(a0);
+      acc[1][q] = st2(a1);
+      acc[2][q] = st2(a2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // ---- field 2: s-pol Bz, p-pol Ex
+  {
+    float2 f[8];
+    z.fwd(G == 0 ? kBz : kEx, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const double C = cC[q], S = cS[q], cS2 = c2 * cS[q];
+      const double2 v = ld2(f[q]);
+      double2 a0 = ld2(acc[0][q]), a2 = ld2(acc[2][q]);
+      if constexpr (G == 0) {
+        a0.x += cS2 * kx * v.y;
+        a0.y -= cS2 * kx * v.x;
+        a2.x += C * v.x;
+        a2.y += C * v.y;
+      } else {
+        a0.x += C * v.x;
+        a0.y += C * v.y;
+        a2.x += S * kz * v.y;
+        a2.y -= S * kz * v.x;
+      }
+      acc[0][q] = st2(a0);
+      acc[2][q] = st2(a2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // ---- field 3: s-pol Ey, p-pol Ez
+  {
+    float2 f[8];
+    z.fwd(G == 0 ? kEy : kEz, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const double C = cC[q], S = cS[q];
+      const double2 v = ld2(f[q]);
+      double2 a0 = ld2(acc[0][q]), a1 = ld2(acc[1][q]), a2 = ld2(acc[2][q]);
+      if constexpr (G == 0) {
+        a0.x += C * v.x;
+        a0.y += C * v.y;
+        a1.x -= S * kz * v.y;
+        a1.y += S * kz * v.x;
+        a2.x += S * kx * v.y;
+        a2.y -= S * kx * v.x;
+      } else {
+        a1.x += C * v.x;
+        a1.y += C * v.y;
+        a2.x -= S * kx * v.y;
+        a2.y += S * kx * v.x;
+      }
+      acc[0][q] = st2(a0);
+      acc[1][q] = st2(a1);
+      acc[2][q] = st2(a2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  z.inv(kO0, acc[0]);
+  z.inv(kO1, acc[1]);
+  z.inv(kO2, acc[2]);
+}
+
+// p-pol (Ex, Ez, By) with sources.  The coefficients are evaluated once, in
+// the first phase; C and S stay in registers and the third coefficient that a
+// later phase needs goes to the thread's own LDS slots (cx[t + 512 q], written
+// and read by the same thread only, so no barrier is involved).
+//   rho form:  rho_old, rho_new: Ex' = i kx R, Ez' = i kz R, R = X3 rho_old - X2 rho_new
+//                                (cx = X1)
+//              Jx: Ex' -= (S/eps0) Jx, By' = i X1 kz Jx
+//              Jz: Ez' -= (S/eps0) Jz, By' -= i X1 kx Jz
+//              By, Ex, Ez: field terms as in vacuum
+//   J form:    Jx, Jz: Ex' = -(S/eps0) Jx - dt X2 kx (k.J), Ez' = -(S/eps0) Jz - dt X2 kz (k.J),
+//                      By' = i X1 (kz Jx - kx Jz)      (cx = L1 = eps0 c^2 X1)
+//              By: field terms as in vacuum
+//              Ex: Ex' += C Ex + L1 kx kx Ex, Ez' += L1 kz kx Ex, By' -= i S kz Ex
+//              Ez: Ez' += C Ez + L1 kz kz Ez, Ex' += L1 kx kz Ez, By' += i S kx Ez
+template <int SRC>
+__device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
+  static_assert(SRC == kRho || SRC == kJForm, "source forms only");
+  const double kx = z.kx, c2 = z.c2;
+  const int t = z.t;
+  float2 acc[3][8];
+  double cC[8], cS[8];
+  if constexpr (SRC == kRho) {
+    {
+      float2 ro[8], rn[8];
+      z.fwd(kRhoOld, ro);
+      z.fwd(kRhoNew, rn);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const double* __restrict__ kzq = P->kz + 512 * q;
-        const double kz = kzq[t];
-        const Coef cf = psatd_coef(sqrt(kx * kx + kz * kz), dt, ph.c, ph.eps0, P->inv_n);
+        const double kz = z.kz_of(q);
+        const Coef cf = z.coef(kz);
         cC[q] = cf.C;
         cS[q] = cf.S;
-        cL[q] = ph.eps0 * ph.c * ph.c * cf.X1;
-        double2 a, b, c;
-        const double2 zero = make_double2(0.0, 0.0);
-        src_2d_p<SRC>(kx, kz, cf, dt, ld2(jx[q]), ld2(jz[q]),
-                      SRC == kRho ? ld2(ro[q]) : zero, SRC == kRho ? ld2(rn[q]) : zero, a, b, c);
-        sc[0][q] = st2(a);
-        sc[1][q] = st2(b);
-        sc[2][q] = st2(c);
+        cx[t + 512 * q] = cf.X1;
+        const double2 o = ld2(ro[q]), n = ld2(rn[q]);
+        const double2 R = make_double2(cf.X3 * o.x - cf.X2 * n.x, cf.X3 * o.y - cf.X2 * n.y);
+        acc[0][q] = st2(make_double2(-kx * R.y, kx * R.x));
+        acc[1][q] = st2(make_double2(-kz * R.y, kz * R.x));
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-  }
-  float2 f[3][8];
-  z_forward(col + kF0 * cs, f[0], bufA, bufB, t, j, k2, w2, w3);
-  z_forward(col + kF1 * cs, f[1], bufA, bufB, t, j, k2, w2, w3);
-  z_forward(col + kF2 * cs, f[2], bufA, bufB, t, j, k2, w2, w3);
+    {
+      float2 f[8];
+      z.fwd(kJx, f);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const double* __restrict__ kzq = P->kz + 512 * q;
-        const double kz = kzq[t];
-    double C, S, L1 = 0.0;
-    double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
-    if constexpr (kSrc) {
-      C = cC[q];
-      S = cS[q];
-      L1 = cL[q];
-      s0 = ld2(sc[0][q]);
-      s1 = ld2(sc[1][q]);
-      s2 = ld2(sc[2][q]);
-    } else {
-      const Coef cf = psatd_coef(sqrt(kx * kx + kz * kz), dt, ph.c, ph.eps0, P->inv_n);
-      C = cf.C;
-      S = cf.S;
+      for (int q = 0; q < 8; ++q) {
+        const double kz = z.kz_of(q);
+        const double Se = cS[q] * z.ie, X1 = cx[t + 512 * q];
+        const double2 v = ld2(f[q]);
+        double2 a0 = ld2(acc[0][q]);
+        a0.x -= Se * v.x;
+        a0.y -= Se * v.y;
+        acc[0][q] = st2(a0);
+        acc[2][q] = st2(make_double2(-X1 * kz * v.y, X1 * kz * v.x));
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
-    double2 a = ld2(f[0][q]), b = ld2(f[1][q]), c = ld2(f[2][q]);
-    if constexpr (G == 0) fld_2d_s(kx, kz, C, S, ph.c, a, b, c, s0, s1, s2);
-    else fld_2d_p<SRC>(kx, kz, C, S, L1, ph.c, a, b, c, s0, s1, s2);
-    f[0][q] = st2(a);
-    f[1][q] = st2(b);
-    f[2][q] = st2(c);
-    __builtin_amdgcn_sched_barrier(0);
+    {
+      float2 f[8];
+      z.fwd(kJz, f);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double Se = cS[q] * z.ie, X1 = cx[t + 512 * q];
+        const double2 v = ld2(f[q]);
+        double2 a1 = ld2(acc[1][q]), a2 = ld2(acc[2][q]);
+        a1.x -= Se * v.x;
+        a1.y -= Se * v.y;
+        a2.x += X1 * kx * v.y;
+        a2.y -= X1 * kx * v.x;
+        acc[1][q] = st2(a1);
+        acc[2][q] = st2(a2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  } else {
+    float2 jx[8], jz[8];
+    z.fwd(kJx, jx);
+    z.fwd(kJz, jz);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const Coef cf = z.coef(kz);
+      cC[q] = cf.C;
+      cS[q] = cf.S;
+      cx[t + 512 * q] = z.eps0 * c2 * cf.X1;
+      double2 a, b, c;
+      const double2 zero = make_double2(0.0, 0.0);
+      src_2d_p<kJForm>(kx, kz, cf, z.dt, ld2(jx[q]), ld2(jz[q]), zero, zero, a, b, c);
+      acc[0][q] = st2(a);
+      acc[1][q] = st2(b);
+      acc[2][q] = st2(c);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  const double2 w2i = cconj(w2), w3i = cconj(w3);
-  const double2* tw4096 = P->fz.tw;
-  z_inverse(f[0], col + kF0 * cs, bufA, bufB, t, j, k2, w2i, w3i, tw4096);
-  z_inverse(f[1], col + kF1 * cs, bufA, bufB, t, j, k2, w2i, w3i, tw4096);
-  z_inverse(f[2], col + kF2 * cs, bufA, bufB, t, j, k2, w2i, w3i, tw4096);
+  // By: Ex' -= i c^2 S kz By, Ez' += i c^2 S kx By, By' += C By
+  {
+    float2 f[8];
+    z.fwd(kBy, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const double C = cC[q], cS2 = c2 * cS[q];
+      const double2 v = ld2(f[q]);
+      double2 a0 = ld2(acc[0][q]), a1 = ld2(acc[1][q]), a2 = ld2(acc[2][q]);
+      a0.x += cS2 * kz * v.y;
+      a0.y -= cS2 * kz * v.x;
+      a1.x -= cS2 * kx * v.y;
+      a1.y += cS2 * kx * v.x;
+      a2.x += C * v.x;
+      a2.y += C * v.y;
+      acc[0][q] = st2(a0);
+      acc[1][q] = st2(a1);
+      acc[2][q] = st2(a2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // Ex: Ex' += C Ex, By' -= i S kz Ex  (J form: Ex' += L1 kx kx Ex, Ez' += L1 kz kx Ex)
+  {
+    float2 f[8];
+    z.fwd(kEx, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const double C = cC[q], S = cS[q];
+      const double2 v = ld2(f[q]);
+      double2 a0 = ld2(acc[0][q]), a2 = ld2(acc[2][q]);
+      a0.x += C * v.x;
+      a0.y += C * v.y;
+      a2.x += S * kz * v.y;
+      a2.y -= S * kz * v.x;
+      if constexpr (SRC == kJForm) {
+        const double L = cx[t + 512 * q];
+        double2 a1 = ld2(acc[1][q]);
+        a0.x += L * kx * kx * v.x;
+        a0.y += L * kx * kx * v.y;
+        a1.x += L * kz * kx * v.x;
+        a1.y += L * kz * kx * v.y;
+        acc[1][q] = st2(a1);
+      }
+      acc[0][q] = st2(a0);
+      acc[2][q] = st2(a2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // Ez: Ez' += C Ez, By' += i S kx Ez  (J form: Ex' += L1 kx kz Ez, Ez' += L1 kz kz Ez)
+  {
+    float2 f[8];
+    z.fwd(kEz, f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double kz = z.kz_of(q);
+      const double C = cC[q], S = cS[q];
+      const double2 v = ld2(f[q]);
+      double2 a1 = ld2(acc[1][q]), a2 = ld2(acc[2][q]);
+      a1.x += C * v.x;
+      a1.y += C * v.y;
+      a2.x -= S * kx * v.y;
+      a2.y += S * kx * v.x;
+      if constexpr (SRC == kJForm) {
+        const double L = cx[t + 512 * q];
+        double2 a0 = ld2(acc[0][q]);
+        a0.x += L * kx * kz * v.x;
+        a0.y += L * kx * kz * v.y;
+        a1.x += L * kz * kz * v.x;
+        a1.y += L * kz * kz * v.y;
+        acc[0][q] = st2(a0);
+      }
+      acc[1][q] = st2(a1);
+      acc[2][q] = st2(a2);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  z.inv(kEx, acc[0]);
+  z.inv(kEz, acc[1]);
+  z.inv(kBy, acc[2]);
 }
 
 template <int SRC>
@@ -476,15 +761,16 @@ z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict_
   extern __shared__ double2 lds2[];
   double2* bufA = lds2;
   double2* bufB = lds2 + kNZ;
-  const int j = threadIdx.x >> 3;
+  double* cx = reinterpret_cast<double*>(lds2 + 2 * kNZ);  // one coefficient per mode
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const WorkItem wi = items[it];
     const PatchDev* P = patches + wi.patch;
-    const double2* tw4096 = P->fz.tw;
-    const double2 w2 = tw4096[64 * (j & 7)];  // exp(-2 pi i (j mod 8) / 64)
-    const double2 w3 = tw4096[8 * j];         // exp(-2 pi i j / 512)
-    z_group<0, SRC>(P, wi.first, ws, ph, bufA, bufB, w2, w3);
-    z_group<1, SRC>(P, wi.first, ws, ph, bufA, bufB, w2, w3);
+    const ZCol z = make_zcol(patches + wi.patch, wi.first, ws, ph, bufA, bufB);
+    z_group<0, SRC>(z);
+    if constexpr (SRC == kVacuum)
+      z_group<1, kVacuum>(z);
+    else
+      z_ppol_sources<SRC>(z, cx);
   }
 }
 
@@ -538,7 +824,7 @@ hipError_t configure_attributes() {
 }
 
 size_t x_lds_bytes() { return sizeof(double) * kRegion * kWaves; }
-size_t z_lds_bytes() { return sizeof(double2) * 2 * kNZ; }
+size_t z_lds_bytes() { return sizeof(double2) * 2 * kNZ + sizeof(double) * kNZ; }
 
 }  // namespace fast2d
 }  // namespace psatd

@@ -97,14 +97,13 @@ __host__ __device__ inline Coef psatd_coef(double K, double dt, double c, double
   const double ih = (h > 0.0) ? 1.0 / h : 0.0;
   const double sinc_h = (h > 0.0) ? sh * ih : 1.0;
   const double sinc_th = sinc_h * ch;  // sin(th)/th = (2 sh ch)/(2 h)
-  double g;
-  if (th < 0.25) {
-    const TrigConsts& T = trig_consts();
-    const double t2 = th * th;
-    g = T.g[0] - t2 * (T.g[1] - t2 * (T.g[2] - t2 * (T.g[3] - t2 * (T.g[4] - t2 * T.g[5]))));
-  } else {
-    g = (1.0 - sinc_th) * (0.25 * ih * ih);  // (1 - sinc th) / th^2
-  }
+  // Both forms are evaluated and one is selected: no divergent branch.
+  const TrigConsts& T = trig_consts();
+  const double t2 = th * th;
+  const double g_series =
+      T.g[0] - t2 * (T.g[1] - t2 * (T.g[2] - t2 * (T.g[3] - t2 * (T.g[4] - t2 * T.g[5]))));
+  const double g_direct = (1.0 - sinc_th) * (0.25 * ih * ih);  // (1 - sinc th) / th^2
+  const double g = (th < 0.25) ? g_series : g_direct;
   const double ie = scale / eps0;
   Coef k;
   k.C = (ch - sh) * (ch + sh) * scale;
@@ -310,7 +309,7 @@ __device__ __forceinline__ void src_2d_p(double kx, double kz, const Coef& q, do
     sEx.y -= b * kx * kdJ.y;
     sEz.x -= b * kz * kdJ.x;
     sEz.y -= b * kz * kdJ.y;
-  } else {
+  } else if constexpr (SRC == kRho) {
     const double2 lam = make_double2(q.X3 * ro.x - q.X2 * rn.x, q.X3 * ro.y - q.X2 * rn.y);
     sEx.x -= kx * lam.y;
     sEx.y += kx * lam.x;
