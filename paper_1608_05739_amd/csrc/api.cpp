@@ -122,6 +122,7 @@ const char* line_pass_name(int kind) {
 struct psatd_plan_s {
   psatd_config cfg{};
   int device = 0;
+  int num_cus = 256;  // compute units of the device (persistent grids)
   int ndim = 2;
   int nin = 6;      // input components
   size_t elem = 4;  // sizeof storage scalar
@@ -445,7 +446,10 @@ Pass make_fast_pass(PassType type, const psatd_plan_s* plan, const std::vector<i
   }
   ps.nitems = static_cast<int>(items.size() - first);
   const size_t lds = type == kFastZ ? fast2d::z_lds_bytes() : fast2d::x_lds_bytes();
-  ps.shape = LaunchShape{ps.nitems, fast2d::kBlock, lds};
+  // The z pass keeps one workgroup per CU (its LDS use allows no more) and
+  // loops over columns, prefetching the next column's first input.
+  const int grid = type == kFastZ ? std::min(ps.nitems, plan->num_cus) : ps.nitems;
+  ps.shape = LaunchShape{grid, fast2d::kBlock, lds};
   ps.bytes = bytes;
   ps.mpt = type == kFastZ ? 8 : 0;
   ps.d_items = reinterpret_cast<WorkItem*>(first);
@@ -736,6 +740,13 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
     psatd_plan_s* plan = new psatd_plan_s();
     plan->cfg = *cfg;
     plan->device = device;
+    {
+      int ncu = 0;
+      if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) ==
+              hipSuccess &&
+          ncu > 0)
+        plan->num_cus = ncu;
+    }
     plan->desc.assign(patches, patches + npatches);
     st = build_plan(plan);
     if (st != PSATD_OK) {

@@ -31,6 +31,19 @@ constexpr int kRegion = kMX + kMX / 16;  // doubles per wave region (padded)
 
 __device__ __forceinline__ int padx(int i) { return i + (i >> 4); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b mod 8, and about 256 run at once, one per CU).  Within each run of 256
+// workgroups this gives XCD x the contiguous items [32 x, 32 x + 32), so that
+// neighbouring tiles, which share 128-byte lines of the [kx][8 z1 + k2]
+// spectra, meet in the same L2.  A bijection on [0, n); the tail past the
+// last full run of 256 keeps its order.
+__device__ __forceinline__ int xcd_local_order(int b, int n) {
+  const int base = b & ~255;
+  if (base + 256 > n) return b;
+  const int r = b & 255;
+  return base + (r & 7) * 32 + (r >> 3);
+}
+
 // Order LDS traffic within one wavefront (no other wave touches the region).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -142,7 +155,7 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
   const int l = threadIdx.x & 63;
   double* region = lds_d + w * kRegion;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const WorkItem wi = items[it];
+    const WorkItem wi = items[xcd_local_order(it, nitems)];
     const PatchDev* P = patches + wi.patch;
     const int z1 = wi.first;
     const double2* tw2048 = P->fx.tw;
@@ -220,7 +233,7 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
   const int l = threadIdx.x & 63;
   double* region = lds_d + w * kRegion;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const WorkItem wi = items[it];
+    const WorkItem wi = items[xcd_local_order(it, nitems)];
     const PatchDev* P = patches + wi.patch;
     const int z1 = wi.first;
     const double2* tw2048 = P->fx.tw;
@@ -346,17 +359,23 @@ __device__ __forceinline__ void fft512_group(double2 (&v)[8], double2* bufA, dou
   DFT<8, SIGN>::run(v);
 }
 
-// Forward transform of one component column into FP32 registers (modes t + 512 q).
-__device__ __forceinline__ void z_forward(const float2* src, float2 (&dst)[8], double2* bufA,
-                                          double2* bufB, int t, int j, int k2,
-                                          const double2* __restrict__ tw4096) {
-  double2 v[8];
-  // uniform base per q plus one 32-bit lane offset (SGPR-base addressing)
+// Loads of one component column into FP32 registers (modes t + 512 q): a
+// uniform base per q plus one 32-bit lane offset (SGPR-base addressing).
+__device__ __forceinline__ void z_load(const float2* src, float2 (&raw)[8], int t) {
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const float2* __restrict__ bq = src + 512 * q;
-    v[q] = ld_f2(bq + t);
+    raw[q] = bq[t];
   }
+}
+
+// Forward transform of one loaded column into FP32 registers.
+__device__ __forceinline__ void z_fft_fwd(const float2 (&raw)[8], float2 (&dst)[8], double2* bufA,
+                                          double2* bufB, int j, int k2,
+                                          const double2* __restrict__ tw4096) {
+  double2 v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = ld2(raw[q]);
   fft512_group<-1>(v, bufA, bufB, j, k2, tw4096);
 #pragma unroll
   for (int q = 0; q < 8; ++q) dst[q] = st2(v[q]);
@@ -395,9 +414,9 @@ struct ZCol {
   double2* bufA;
   double2* bufB;
 
-  // The empty asm makes every read of kz opaque to the optimizer: the
-  // coefficients are recomputed on purpose in later phases, and merging those
-  // evaluations would keep them live across the transforms in between.
+  // The empty asm makes every read of kz opaque to the optimizer: the s and p
+  // groups evaluate the same coefficients, and merging the two evaluations
+  // would keep them live across the s group's inverse transforms.
   __device__ __forceinline__ double kz_of(int q) const {
     const double* __restrict__ kzq = kz + 512 * q;
     double v = kzq[t];
@@ -407,8 +426,18 @@ struct ZCol {
   __device__ __forceinline__ Coef coef(double kzv) const {
     return psatd_coef(sqrt(kx * kx + kzv * kzv), dt, c, eps0, scale);
   }
-  __device__ __forceinline__ void fwd(int comp, float2 (&dst)[8]) const {
-    z_forward(col + comp * cs, dst, bufA, bufB, t, j, k2, tw);
+  __device__ __forceinline__ const float2* src(int comp) const { return col + comp * cs; }
+  // Software pipeline: `pre` holds the loads issued one phase earlier.  Issue
+  // the loads of `next` into `pre`, then transform the previous contents into
+  // `dst`, so that the HBM latency of the next input overlaps this transform
+  // and the update that follows it.
+  __device__ __forceinline__ void fwd(float2 (&pre)[8], const float2* next,
+                                      float2 (&dst)[8]) const {
+    float2 cur[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cur[q] = pre[q];
+    z_load(next, pre, t);
+    z_fft_fwd(cur, dst, bufA, bufB, j, k2, tw);
   }
   __device__ __forceinline__ void inv(int comp, const float2 (&src)[8]) const {
     z_inverse(src, col + comp * cs, bufA, bufB, t, j, k2, tw);
@@ -453,7 +482,7 @@ __device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* w
 //   Ez: Ez' += C Ez,  By' += i S kx Ez
 // (p-pol with sources: z_ppol_sources.)
 template <int G, int SRC>
-__device__ __forceinline__ void z_group(const ZCol& z) {
+__device__ __forceinline__ void z_group(const ZCol& z, float2 (&pre)[8], const float2* next) {
   static_assert(G == 0 || SRC == kVacuum, "p-pol with sources has its own schedule");
   constexpr bool kSrc = SRC != kVacuum;
   constexpr int kO0 = G == 0 ? kEy : kEx;
@@ -466,7 +495,7 @@ __device__ __forceinline__ void z_group(const ZCol& z) {
 
   if constexpr (kSrc) {
     float2 jy[8];
-    z.fwd(kJy, jy);
+    z.fwd(pre, z.src(kBx), jy);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -485,7 +514,7 @@ __device__ __forceinline__ void z_group(const ZCol& z) {
   // ---- field 1: s-pol Bx, p-pol By
   {
     float2 f[8];
-    z.fwd(G == 0 ? kBx : kBy, f);
+    z.fwd(pre, z.src(G == 0 ? kBz : kEx), f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -521,7 +550,7 @@ __device__ __forceinline__ void z_group(const ZCol& z) {
   // ---- field 2: s-pol Bz, p-pol Ex
   {
     float2 f[8];
-    z.fwd(G == 0 ? kBz : kEx, f);
+    z.fwd(pre, z.src(G == 0 ? kEy : kEz), f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -547,7 +576,7 @@ __device__ __forceinline__ void z_group(const ZCol& z) {
   // ---- field 3: s-pol Ey, p-pol Ez
   {
     float2 f[8];
-    z.fwd(G == 0 ? kEy : kEz, f);
+    z.fwd(pre, next, f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -593,7 +622,8 @@ __device__ __forceinline__ void z_group(const ZCol& z) {
 //              Ex: Ex' += C Ex + L1 kx kx Ex, Ez' += L1 kz kx Ex, By' -= i S kz Ex
 //              Ez: Ez' += C Ez + L1 kz kz Ez, Ex' += L1 kx kz Ez, By' += i S kx Ez
 template <int SRC>
-__device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
+__device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx, float2 (&pre)[8],
+                                               const float2* next) {
   static_assert(SRC == kRho || SRC == kJForm, "source forms only");
   const double kx = z.kx, c2 = z.c2;
   const int t = z.t;
@@ -602,8 +632,8 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
   if constexpr (SRC == kRho) {
     {
       float2 ro[8], rn[8];
-      z.fwd(kRhoOld, ro);
-      z.fwd(kRhoNew, rn);
+      z.fwd(pre, z.src(kRhoNew), ro);
+      z.fwd(pre, z.src(kJx), rn);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double kz = z.kz_of(q);
@@ -620,7 +650,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
     }
     {
       float2 f[8];
-      z.fwd(kJx, f);
+      z.fwd(pre, z.src(kJz), f);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double kz = z.kz_of(q);
@@ -636,7 +666,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
     }
     {
       float2 f[8];
-      z.fwd(kJz, f);
+      z.fwd(pre, z.src(kBy), f);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double Se = cS[q] * z.ie, X1 = cx[t + 512 * q];
@@ -653,8 +683,8 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
     }
   } else {
     float2 jx[8], jz[8];
-    z.fwd(kJx, jx);
-    z.fwd(kJz, jz);
+    z.fwd(pre, z.src(kJz), jx);
+    z.fwd(pre, z.src(kBy), jz);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -674,7 +704,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
   // By: Ex' -= i c^2 S kz By, Ez' += i c^2 S kx By, By' += C By
   {
     float2 f[8];
-    z.fwd(kBy, f);
+    z.fwd(pre, z.src(kEx), f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -696,7 +726,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
   // Ex: Ex' += C Ex, By' -= i S kz Ex  (J form: Ex' += L1 kx kx Ex, Ez' += L1 kz kx Ex)
   {
     float2 f[8];
-    z.fwd(kEx, f);
+    z.fwd(pre, z.src(kEz), f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -724,7 +754,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
   // Ez: Ez' += C Ez, By' += i S kx Ez  (J form: Ex' += L1 kx kz Ez, Ez' += L1 kz kz Ez)
   {
     float2 f[8];
-    z.fwd(kEz, f);
+    z.fwd(pre, next, f);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double kz = z.kz_of(q);
@@ -754,6 +784,13 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx) {
   z.inv(kBy, acc[2]);
 }
 
+// First input of the s group and of the p group, in processing order.
+template <int SRC>
+struct ZOrder {
+  static constexpr int kFirstS = SRC == kVacuum ? kBx : kJy;
+  static constexpr int kFirstP = SRC == kVacuum ? kBy : (SRC == kRho ? kRhoOld : kJx);
+};
+
 template <int SRC>
 __global__ void __launch_bounds__(512)
 z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
@@ -762,15 +799,30 @@ z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict_
   double2* bufA = lds2;
   double2* bufB = lds2 + kNZ;
   double* cx = reinterpret_cast<double*>(lds2 + 2 * kNZ);  // one coefficient per mode
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const WorkItem wi = items[it];
-    const PatchDev* P = patches + wi.patch;
-    const ZCol z = make_zcol(patches + wi.patch, wi.first, ws, ph, bufA, bufB);
-    z_group<0, SRC>(z);
+  int it = blockIdx.x;
+  if (it >= nitems) return;
+  int patch = items[it].patch, kxcol = items[it].first;
+  float2 pre[8];
+  z_load(make_zcol(patches + patch, kxcol, ws, ph, bufA, bufB).src(ZOrder<SRC>::kFirstS), pre,
+         threadIdx.x);
+  for (; it < nitems; it += gridDim.x) {
+    const ZCol z = make_zcol(patches + patch, kxcol, ws, ph, bufA, bufB);
+    // The p group's last phase prefetches the next column's first input; after
+    // the last column it re-reads this column's (never used).
+    const int nit = it + gridDim.x;
+    const bool more = nit < nitems;
+    const int npatch = more ? items[nit].patch : patch;
+    const int nkx = more ? items[nit].first : kxcol;
+    const PatchDev* Pn = patches + npatch;
+    const float2* next = reinterpret_cast<const float2*>(ws) + Pn->off_spec +
+                         (long long)nkx * kNZ + ZOrder<SRC>::kFirstS * Pn->comp_stride;
+    z_group<0, SRC>(z, pre, z.src(ZOrder<SRC>::kFirstP));
     if constexpr (SRC == kVacuum)
-      z_group<1, kVacuum>(z);
+      z_group<1, kVacuum>(z, pre, next);
     else
-      z_ppol_sources<SRC>(z, cx);
+      z_ppol_sources<SRC>(z, cx, pre, next);
+    patch = npatch;
+    kxcol = nkx;
   }
 }
 
