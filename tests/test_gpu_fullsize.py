@@ -67,3 +67,66 @@ def test_fast_path_matches_generic_kernels(w1):
     err = rel_l2(a, b)
     say(f"  rel L2 (fast vs generic) = {err:.3e}")
     assert err < 2e-6
+
+
+def _oracle_inputs(w):
+    E = [np.asarray(a, np.float32).astype(np.float64) for a in w.E0[0]]
+    B = [np.asarray(a, np.float32).astype(np.float64) for a in w.B0[0]]
+    return E, B
+
+
+def test_fullsize_1000_steps_vacuum_vs_one_oracle_step(w1):
+    """1000 vacuum steps of dt on the GPU equal one oracle step of 1000 dt
+    (the update is the exact flow of each mode; the semigroup pin of the
+    oracle covers this identity)."""
+    import torch
+    p = w1.patches[0]
+    K = 1000
+    say(f"vacuum, {K} steps at 4096x4096 (graph) vs one oracle step of {K} dt")
+    plan = pk.Plan([p], precision="fp32", source_mode="vacuum", path="fused", graph=True)
+    E = [_dev(a) for a in w1.E0[0]]
+    B = [_dev(a) for a in w1.B0[0]]
+    plan.push(E, B, steps=K)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    E0, B0 = _oracle_inputs(w1)
+    En, Bn = oracle.psatd_step(E0, B0, d=p.d, dt=K * p.dt)
+    err = rel_l2(got, En + Bn)
+    say(f"  rel L2 after {K} steps = {err:.3e}")
+    assert err < 1e-5
+
+
+def test_fullsize_1000_steps_sources_vs_one_oracle_step(w1):
+    """1000 steps with J held at J^(1/2) and rho linear in time (rho^n = -n dt
+    div J, exact discrete continuity) equal one oracle step of 1000 dt with
+    the same J, rho_old = 0 and rho_new = -1000 dt div J."""
+    import torch
+    p = w1.patches[0]
+    K = 1000
+    J, _ro, rn = w1.schedule[0].sources(0, dtype=np.float64)  # rho^0 = 0, rho^1 = -dt div J
+    divJ = -rn / p.dt
+    J32 = [np.asarray(a, np.float32) for a in J]
+    divJ32 = np.asarray(divJ, np.float32)
+    say(f"rho form, {K} steps at 4096x4096, constant J, linear rho, vs one oracle step")
+    plan = pk.Plan([p], precision="fp32", source_mode="rho", path="fused", graph=True)
+    E = [_dev(a) for a in w1.E0[0]]
+    B = [_dev(a) for a in w1.B0[0]]
+    Jd = [_dev(a) for a in J32]
+    dd = _dev(divJ32)
+    ro = torch.empty_like(dd)
+    rn_d = torch.empty_like(dd)
+    for n in range(K):
+        torch.mul(dd, -n * p.dt, out=ro)
+        torch.mul(dd, -(n + 1) * p.dt, out=rn_d)
+        plan.push(E, B, Jd, ro, rn_d, steps=1)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    E0, B0 = _oracle_inputs(w1)
+    Jo = [a.astype(np.float64) for a in J32]
+    rho_new = -K * p.dt * divJ32.astype(np.float64)
+    En, Bn = oracle.psatd_step(E0, B0, Jo, np.zeros_like(rho_new), rho_new, d=p.d, dt=K * p.dt)
+    err = rel_l2(got, En + Bn)
+    say(f"  rel L2 after {K} steps = {err:.3e}")
+    assert err < 1e-5
