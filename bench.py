@@ -61,6 +61,16 @@ def measured_traffic(workload, kernel):
     return ent.get("bytes_per_launch")
 
 
+def plan_grids(plan):
+    """Launch grid of each pass, as the plan reports it (after autotuning)."""
+    out = {}
+    for line in plan.info.splitlines()[1:]:
+        parts = line.split()
+        if parts and any(p.startswith("grid=") for p in parts):
+            out[parts[0]] = int(next(p for p in parts if p.startswith("grid="))[5:])
+    return out
+
+
 def build_inputs(index, steps, npatches=None):
     import fixtures
 
@@ -150,7 +160,8 @@ def run_fp64(pk, w, mode, cells, steps, args, vacuum_batch):
     """The plain FP64 path on the same workload (reported beside the FP32 one)."""
     import torch
 
-    plan64 = pk.Plan(w.patches, precision="fp64", source_mode=mode, path="plain", graph=True)
+    plan64 = pk.Plan(w.patches, precision="fp64", source_mode=mode, path="plain", graph=True,
+                     autotune=True)
     E64, B64, J64, ro64, rn64 = device_fields(w, plan64, np.float64)
     E64_1 = [t.clone() for t in E64]
     B64_1 = [t.clone() for t in B64]
@@ -212,7 +223,8 @@ def main():
     cells = w.cells
 
     # ------------------------------------------------ FP32 storage, fused path
-    plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", graph=True)
+    plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", graph=True,
+                   autotune=True)
     log("[bench] fp32 fused plan:\n" + plan.info)
     E, B, J, ro, rn = device_fields(w, plan, np.float32)
     # one-step parity spot check on the same inputs (before timing mutates E, B)
@@ -229,8 +241,9 @@ def main():
     pass_ms = plan.push_profiled(E, B, J, ro, rn, steps=prof_steps) if not vacuum_batch else \
         plan.push_profiled(E, B, steps=prof_steps)
     names, pbytes = plan.pass_names, plan.pass_bytes
+    grids = plan_grids(plan)
     passes = {n: {"ms": round(m, 5), "model_GBps": round(b / (m * 1e-3) / 1e9, 1),
-                  "model_bytes": b} for n, m, b in zip(names, pass_ms, pbytes)}
+                  "model_bytes": b, "grid": grids.get(n)} for n, m, b in zip(names, pass_ms, pbytes)}
     dom = int(np.argmax(pass_ms))
     achieved = pbytes[dom] / (pass_ms[dom] * 1e-3) / 1e9
     step_bytes = sum(pbytes)

@@ -64,7 +64,7 @@ enum { PSATD_VACUUM = 0, PSATD_SOURCES_RHO = 1, PSATD_SOURCES_J = 2 }; /* update
 enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel composition */
 
 /* psatd_config.flags */
-#define PSATD_FLAG_AUTOTUNE 0x1u /* time candidate launch shapes at plan time, keep the fastest */
+#define PSATD_FLAG_AUTOTUNE 0x1u /* time each pass at several grid sizes at plan time (on scratch fields), keep the fastest */
 #define PSATD_FLAG_GRAPH 0x2u    /* replay a captured hipGraph of one step inside psatd_push   */
 #define PSATD_FLAG_NO_WORKSPACE 0x4u /* allocate no workspace: call psatd_set_workspace first */
 #define PSATD_FLAG_GENERIC_KERNELS 0x8u /* never pick shape-specialized kernels (cross-checks) */

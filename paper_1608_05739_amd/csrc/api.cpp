@@ -104,6 +104,7 @@ struct Pass {
   int nitems = 0;
   double bytes = 0.0;
   int mpt = 0;
+  double tuned_ms = -1.0;  // mean launch time at the chosen grid (autotune), else -1
 };
 
 const char* line_pass_name(int kind) {
@@ -446,8 +447,11 @@ Pass make_fast_pass(PassType type, const psatd_plan_s* plan, const std::vector<i
   }
   ps.nitems = static_cast<int>(items.size() - first);
   const size_t lds = type == kFastZ ? fast2d::z_lds_bytes() : fast2d::x_lds_bytes();
-  // The z pass keeps one workgroup per CU (its LDS use allows no more) and
-  // loops over columns, prefetching the next column's first input.
+  // Each kernel fits one workgroup per CU (LDS) and loops over its items when
+  // the grid is smaller than the item count.  Default grids as measured at
+  // 4096x4096: the z pass walks its columns (prefetching the next one); the x
+  // passes do better with one workgroup per item, handed out by the hardware
+  // as CUs free up.  PSATD_FLAG_AUTOTUNE re-measures.
   const int grid = type == kFastZ ? std::min(ps.nitems, plan->num_cus) : ps.nitems;
   ps.shape = LaunchShape{grid, fast2d::kBlock, lds};
   ps.bytes = bytes;
@@ -527,6 +531,94 @@ psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStre
 
 bool same_fields(const FieldPtrs& a, const FieldPtrs& b) {
   return std::memcmp(&a, &b, sizeof(FieldPtrs)) == 0;
+}
+
+// Launch-shape autotuning (PSATD_FLAG_AUTOTUNE).  Every kernel loops over its
+// work list, so any grid size is correct; what changes is whether one
+// workgroup per CU walks the list (and prefetches its next item) or the
+// hardware hands out items as CUs free up.  Each pass is timed alone, at each
+// candidate grid, on zero-filled scratch fields (the work does not depend on
+// the values), and keeps the fastest.
+psatd_status autotune_passes(psatd_plan_s* plan) {
+  long long total = 0;
+  for (const psatd_patch_desc& d : plan->desc)
+    total = std::max<long long>(total, d.offset + d.n[0] * d.n[1] * d.n[2]);
+  const size_t comp_bytes = static_cast<size_t>(total) * plan->elem;
+  void* fields = nullptr;
+  void* tmp_ws = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  psatd_status st = PSATD_OK;
+  auto cleanup = [&]() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (fields) (void)hipFree(fields);
+    if (tmp_ws) {
+      (void)hipFree(tmp_ws);
+      plan->ws = nullptr;
+    }
+  };
+  hipError_t e = hipMalloc(&fields, comp_bytes * plan->nin);
+  if (e != hipSuccess) {
+    fields = nullptr;
+    cleanup();
+    return fail(PSATD_ERR_OOM, "autotune: scratch fields");
+  }
+  e = hipMemset(fields, 0, comp_bytes * plan->nin);
+  if (e == hipSuccess && !plan->ws) {
+    e = hipMalloc(&tmp_ws, plan->ws_bytes);
+    if (e == hipSuccess) {
+      plan->ws = tmp_ws;
+      e = hipMemset(tmp_ws, 0, plan->ws_bytes);
+    } else {
+      tmp_ws = nullptr;
+    }
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "autotune setup");
+  }
+  FieldPtrs f{};
+  for (int c = 0; c < plan->nin; ++c) f.f[c] = static_cast<char*>(fields) + c * comp_bytes;
+  constexpr int kReps = 3;
+  for (Pass& ps : plan->passes) {
+    std::vector<int> cands = {ps.nitems};
+    for (int k : {1, 2, 4})
+      if (k * plan->num_cus < ps.nitems) cands.push_back(k * plan->num_cus);
+    int best = ps.shape.grid;
+    double best_ms = 1e300;
+    for (int g : cands) {
+      ps.shape.grid = g;
+      st = enqueue_pass(plan, ps, f, s);  // warm-up
+      if (st != PSATD_OK) break;
+      e = hipEventRecord(e0, s);
+      for (int r = 0; r < kReps && st == PSATD_OK && e == hipSuccess; ++r)
+        st = enqueue_pass(plan, ps, f, s);
+      if (st != PSATD_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      const double per = ms / kReps;
+      if (per < best_ms) {
+        best_ms = per;
+        best = g;
+      }
+    }
+    ps.shape.grid = best;
+    if (st != PSATD_OK || e != hipSuccess) break;
+    ps.tuned_ms = best_ms;
+  }
+  cleanup();
+  if (st != PSATD_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  return PSATD_OK;
 }
 
 psatd_status build_plan(psatd_plan_s* plan) {
@@ -696,6 +788,10 @@ psatd_status build_plan(psatd_plan_s* plan) {
   }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "plan tables");
+  if (cfg.flags & PSATD_FLAG_AUTOTUNE) {
+    psatd_status st = autotune_passes(plan);
+    if (st != PSATD_OK) return st;
+  }
 
   char buf[512];
   plan->info.clear();
@@ -705,8 +801,9 @@ psatd_status build_plan(psatd_plan_s* plan) {
                 plan->ws_bytes);
   plan->info += buf;
   for (const Pass& ps : plan->passes) {
-    std::snprintf(buf, sizeof(buf), "  %-10s items=%d block=%d lds=%zu mpt=%d bytes=%.0f\n",
-                  ps.name, ps.nitems, ps.shape.block, ps.shape.lds_bytes, ps.mpt, ps.bytes);
+    std::snprintf(buf, sizeof(buf), "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d bytes=%.0f%s\n",
+                  ps.name, ps.nitems, ps.shape.grid, ps.shape.block, ps.shape.lds_bytes, ps.mpt,
+                  ps.bytes, ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
     plan->info += buf;
   }
   return PSATD_OK;

@@ -147,6 +147,26 @@ __device__ __forceinline__ double2 ld_f2(const float2* p) {
 // ------------------------------------------------------------------ P1
 // Forward: rows z1 + 512 z2 (z2 = wave) of component `comp` -> r2c along x ->
 // 8-point DFT over z2 and twiddle W4096^(z1 k2) -> spectra [kx][8 z1 + k2].
+//
+// A workgroup loops over tiles when the grid is smaller than the tile count.
+// The FFT state is dead during a tile's output phase, so the wave then loads
+// its next tile's row (FP32) into registers there: the HBM latency of that load
+// overlaps the output phase instead of stalling the next tile's FFT.
+
+__device__ __forceinline__ const float2* x_row(const PatchDev* P, const FieldPtrs& fields,
+                                               const WorkItem& wi, int w) {
+  return reinterpret_cast<const float2*>(static_cast<const float*>(fields.f[wi.comp]) +
+                                         P->off_real + (long long)(wi.first + kN1 * w) * (2 * kMX));
+}
+
+// lane l loads z[l + 64 b + 128 q] of the packed row (z[m] = x[2m] + i x[2m+1])
+__device__ __forceinline__ void x_load_row(const float2* row, float2 (&raw)[2][16], int l) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) raw[b][q] = row[l + 64 * b + 128 * q];
+}
+
 __global__ void __launch_bounds__(512)
 x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
              int nitems, FieldPtrs fields, float* __restrict__ ws) {
@@ -154,7 +174,14 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   double* region = lds_d + w * kRegion;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  int it = blockIdx.x;
+  if (it >= nitems) return;
+  float2 raw[2][16];
+  {
+    const WorkItem wi = items[xcd_local_order(it, nitems)];
+    x_load_row(x_row(patches + wi.patch, fields, wi, w), raw, l);
+  }
+  for (; it < nitems; it += gridDim.x) {
     const WorkItem wi = items[xcd_local_order(it, nitems)];
     const PatchDev* P = patches + wi.patch;
     const int z1 = wi.first;
@@ -165,15 +192,11 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 #pragma unroll
     for (int b = 0; b < 4; ++b) twC[b] = tw2048[l + 64 * b];
 
-    // load row z = z1 + 512 w as complex pairs
-    const float2* row = reinterpret_cast<const float2*>(
-        static_cast<const float*>(fields.f[wi.comp]) + P->off_real +
-        (long long)(z1 + kN1 * w) * (2 * kMX));
     double2 a[2][16];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) a[b][q] = ld_f2(row + l + 64 * b + 128 * q);
+      for (int q = 0; q < 16; ++q) a[b][q] = make_double2(raw[b][q].x, raw[b][q].y);
     double2 c[4][8];
     wave_fft2048<-1>(region, a, c, twB, twC);
     // stage Z (FP32) into this wave's region: Z[m] at float2 index m
@@ -185,6 +208,13 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
         zrow[l + 64 * b + 256 * q] = make_float2(static_cast<float>(c[b][q].x),
                                                  static_cast<float>(c[b][q].y));
     __syncthreads();
+
+    // next tile's row (the same workgroup's next item), in flight during the output phase
+    const int nit = it + gridDim.x;
+    if (nit < nitems) {
+      const WorkItem wn = items[xcd_local_order(nit, nitems)];
+      x_load_row(x_row(patches + wn.patch, fields, wn, w), raw, l);
+    }
 
     // output phase: kx = t + 512 i
     double2 tz[8];

@@ -28,11 +28,11 @@ def _host(t, shape):
     return t.detach().cpu().numpy().astype(np.float64).reshape(shape)
 
 
-def _run(w, steps, generic=False, n0=0):
+def _run(w, steps, generic=False, n0=0, autotune=False):
     import torch
     p = w.patches[0]
     plan = pk.Plan([p], precision="fp32", source_mode="rho", path="fused",
-                   generic_kernels=generic)
+                   generic_kernels=generic, autotune=autotune)
     E = [_dev(a) for a in w.E0[0]]
     B = [_dev(a) for a in w.B0[0]]
     for n in range(n0, n0 + steps):
@@ -67,6 +67,16 @@ def test_fast_path_matches_generic_kernels(w1):
     err = rel_l2(a, b)
     say(f"  rel L2 (fast vs generic) = {err:.3e}")
     assert err < 2e-6
+
+
+def test_fullsize_autotuned_plan_is_bitwise_identical(w1):
+    """The launch configuration bench.py times (autotuned grids) computes
+    exactly what the default configuration computes."""
+    say("autotuned vs default grids, 2 steps at 4096x4096")
+    a, _ = _run(w1, 2, autotune=True)
+    b, _ = _run(w1, 2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
 
 
 def _oracle_inputs(w):

@@ -131,3 +131,31 @@ def test_repeated_runs_bitwise_identical():
     for pa, pb in zip(a[0] + a[1], b[0] + b[1]):
         for x, y in zip(pa, pb):
             assert np.array_equal(x, y)
+
+
+def test_autotuned_plan_is_bitwise_identical():
+    """Autotuning changes launch grids only: every item still runs the same
+    arithmetic, so results are bitwise identical to the default plan."""
+    import torch
+    import fixtures
+    import paper_1608_05739_amd as pk
+    w = fixtures.workload(3, npatches=6)
+    outs = []
+    for tune in (False, True):
+        plan = pk.Plan(w.patches, precision="fp32", source_mode="vacuum", path="fused",
+                       autotune=tune)
+        if tune:
+            assert "(autotuned)" in plan.info
+        E, B = [], []
+        for c in range(3):
+            for lst, src in ((E, w.E0), (B, w.B0)):
+                flat = np.zeros(plan.total_elements, np.float32)
+                for off, fields in zip(plan.offsets, src):
+                    flat[off:off + fields[c].size] = fields[c].ravel()
+                lst.append(torch.from_numpy(flat).to("cuda:0"))
+        plan.push(E, B, steps=3)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in E + B])
+        plan.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
