@@ -105,7 +105,8 @@ typedef struct {
 psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches,
                         int32_t npatches, int32_t device, psatd_plan_t* out);
 
-/* Bytes of device workspace the plan needs (the k-space spectra of all inputs). */
+/* Bytes of device workspace the plan needs: the k-space spectra of all inputs
+ * (twice that in 3D, where the y passes move them between two blocks). */
 psatd_status psatd_workspace_size(psatd_plan_t plan, size_t* bytes);
 
 /* Hand the plan a caller-owned device workspace of at least

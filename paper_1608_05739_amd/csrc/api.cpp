@@ -735,6 +735,9 @@ psatd_status build_plan(psatd_plan_s* plan) {
       e = launch_twiddles(const_cast<double2*>(P.post), P.nx, P.mx, nullptr);
     if (e != hipSuccess) return hip_fail(e, "k tables");
   }
+  // 3D: a second block of the same size for the z passes (see PatchDev::off_z)
+  for (PatchDev& P : plan->host_patches) P.off_z = plan->ndim == 3 ? spec_off + P.off_spec : P.off_spec;
+  if (plan->ndim == 3) spec_off *= 2;
   plan->ws_bytes = static_cast<size_t>(spec_off) * 2 * plan->elem;
 
   e = hipMalloc(&plan->d_patches, sizeof(PatchDev) * plan->host_patches.size());

@@ -31,7 +31,8 @@ struct FFTPlanDev {
 // input component; after the x pass the x axis is halved to mx = nx/2 complex
 // columns, column 0 carrying the DC and Nyquist planes packed as re + i*im.
 //   2D spectra  [kx][z]           (lines along z contiguous)
-//   3D spectra  [z][kx][y] after the x pass, [kx][y][z] after the y pass.
+//   3D spectra  [z][kx][y] after the x pass (block off_spec),
+//               [kx][y][z] after the y pass (block off_z).
 struct PatchDev {
   int ndim;
   int nx, ny, nz, mx;
@@ -40,6 +41,10 @@ struct PatchDev {
   double inv_n;           // 1 / (nx ny nz), folded into the update
   long long off_real;     // element offset in the caller's component buffers
   long long off_spec;     // complex-element offset of this patch's first component
+  long long off_z;        // block the z passes work on: off_spec in 2D; in 3D a second
+                          // block, so that the y passes, which change the layout, read
+                          // one block and write the other (never lines another
+                          // workgroup of the same pass has still to read)
   long long comp_stride;  // complex elements per component block (mx ny nz)
   const double* kx;       // [mx]  k_x of packed column j (column 0: k_x = 0)
   const double* ky;       // [ny]

@@ -146,7 +146,12 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
     const int l0 = wi.first;
     const int LS = L;
     const int total = nl * L;
-    V* spec = reinterpret_cast<V*>(ws) + P->off_spec + (long long)wi.comp * P->comp_stride;
+    // x passes use block off_spec, z passes block off_z; the y passes read one
+    // and write the other (forward: off_spec -> off_z; inverse: off_z -> off_spec)
+    V* const blk_x = reinterpret_cast<V*>(ws) + P->off_spec + (long long)wi.comp * P->comp_stride;
+    V* const blk_z = reinterpret_cast<V*>(ws) + P->off_z + (long long)wi.comp * P->comp_stride;
+    V* spec = (KIND == kXFwd || KIND == kXInv || KIND == kYFwd) ? blk_x : blk_z;  // loads
+    V* spec_out = (KIND == kXFwd || KIND == kXInv || KIND == kYInv) ? blk_x : blk_z;  // stores
 
     // ---------------- load
     if constexpr (KIND == kXFwd) {
@@ -188,7 +193,7 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
         const int n = idx / nl;
         const int r = idx - n * nl;
         const long long l = l0 + r;
-        spec[(l % tm.A) + (l / tm.A) * tm.B + n * tm.C] = from_d2<V>(lds[r * LS + n]);
+        spec_out[(l % tm.A) + (l / tm.A) * tm.B + n * tm.C] = from_d2<V>(lds[r * LS + n]);
       }
     } else if constexpr (KIND == kXInv) {
       V* dst = reinterpret_cast<V*>(static_cast<S*>(fields.f[wi.comp]) + P->off_real);
@@ -201,10 +206,10 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
       for (int idx = threadIdx.x; idx < total; idx += T) {
         const int r = idx / L;
         const int n = idx - r * L;
-        spec[yline_start(P, l0 + r) + n] = from_d2<V>(lds[r * LS + n]);
+        spec_out[yline_start(P, l0 + r) + n] = from_d2<V>(lds[r * LS + n]);
       }
     } else {
-      V* dst = spec + (long long)l0 * L;
+      V* dst = spec_out + (long long)l0 * L;
       for (int idx = threadIdx.x; idx < total; idx += T) dst[idx] = from_d2<V>(lds[idx]);
     }
     __syncthreads();
@@ -223,7 +228,7 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
   const int nz = P->nz;
   const int W = wi.count;
   const int nmodes = W * nz;
-  V* base = reinterpret_cast<V*>(ws) + P->off_spec + (long long)wi.first * nz;
+  V* base = reinterpret_cast<V*>(ws) + P->off_z + (long long)wi.first * nz;
   const long long cs = P->comp_stride;
   const FFTPlanDev* F = &P->fz;
 
@@ -342,7 +347,7 @@ update_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const WorkItem wi = items[it];
     const PatchDev* P = patches + wi.patch;
-    V* base = reinterpret_cast<V*>(ws) + P->off_spec;
+    V* base = reinterpret_cast<V*>(ws) + P->off_z;
     const long long cs = P->comp_stride;
     const int nz = P->nz;
     const double dt = P->dt;
