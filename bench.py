@@ -61,6 +61,56 @@ def measured_traffic(workload, kernel):
     return ent.get("bytes_per_launch")
 
 
+PASS_OF_KERNEL = (("x_fwd_kernel", "x_r2c_fwd"), ("z_fused_kernel", "z_fused"),
+                  ("x_inv_kernel", "x_c2r_inv"))
+
+
+def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, both with --copy-calibration-mib) into HBM bytes per launch
+    of each pass, scaled by what the counters read for the calibration copy,
+    and store them in profiles/traffic.json with the kernel-source hash."""
+    import csv
+    import fixtures
+
+    def rows(path, counter):
+        out = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return out
+
+    fetch, write = rows(fetch_csv, "FETCH_SIZE"), rows(write_csv, "WRITE_SIZE")
+    kib = calib_mib * 1024.0
+    # the calibration copy: the first copy kernel whose WRITE_SIZE is the copied size
+    wcal = next(v for n, v in write if "copy" in n.lower() and abs(v - kib) < 0.01 * kib)
+    fcal = next(v for n, v in fetch if "copy" in n.lower() and 0.3 * kib < v < 1.2 * kib)
+    fscale, wscale = kib / fcal, kib / wcal
+    name = fixtures.CONFIG_NAMES[workload_index]
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    h = kernel_source_hash()
+    for key, pname in PASS_OF_KERNEL:
+        fv = [v for n, v in fetch if key in n]
+        wv = [v for n, v in write if key in n]
+        if not fv or not wv:
+            continue
+        f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
+        data[f"{name}:{pname}"] = {
+            "bytes_per_launch": (f_kib * fscale + w_kib * wscale) * 1024.0,
+            "fetch_kib": f_kib, "write_kib": w_kib, "fetch_scale": fscale, "write_scale": wscale,
+            "dispatches": len(fv), "source_hash": h}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return data
+
+
 def plan_grids(plan):
     """Launch grid of each pass, as the plan reports it (after autotuning)."""
     out = {}
@@ -194,7 +244,15 @@ def main():
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no run: store HBM bytes per pass from two rocprofv3 --pmc counter "
+                         "files (FETCH_SIZE, WRITE_SIZE) of this script, scaled by its "
+                         "calibration copy (--copy-calibration-mib, default 1024)")
     args = ap.parse_args()
+    if args.ingest_traffic:
+        data = ingest_traffic(*args.ingest_traffic, args.workload, args.copy_calibration_mib or 1024)
+        print(json.dumps(data, indent=1, sort_keys=True))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}); use --gpus 1", file=sys.stderr)
