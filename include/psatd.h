@@ -68,6 +68,11 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
 #define PSATD_FLAG_GRAPH 0x2u    /* replay a captured hipGraph of one step inside psatd_push   */
 #define PSATD_FLAG_NO_WORKSPACE 0x4u /* allocate no workspace: call psatd_set_workspace first */
 #define PSATD_FLAG_GENERIC_KERNELS 0x8u /* never pick shape-specialized kernels (cross-checks) */
+/* order p > 0: take k_p from the centered (collocated) order-p stencil,
+ * sum_l a_l (2/d) sin(l k d), instead of the staggered one of Sec. III.B.
+ * Its symbol vanishes smoothly at the Nyquist wavenumber, so every operator of
+ * the step stays local in real space (what guard-cell decompositions need). */
+#define PSATD_FLAG_CENTERED_STENCIL 0x10u
 
 typedef struct {
   int32_t ndim;  /* 2: (x, z) plane, n[1] must be 1;  3: (x, y, z)                   */
@@ -82,7 +87,8 @@ typedef struct {
   int32_t precision;   /* PSATD_FP32 or PSATD_FP64                                    */
   int32_t source_mode; /* PSATD_VACUUM, PSATD_SOURCES_RHO or PSATD_SOURCES_J          */
   int32_t path;        /* PSATD_PATH_FUSED or PSATD_PATH_PLAIN                        */
-  int32_t order;       /* 0: exact k; even p >= 2: order-p stencil wavevector k_p     */
+  int32_t order;       /* 0: exact k; even p >= 2: order-p stencil wavevector k_p
+                          (staggered stencil, or centered with the flag below)      */
   double c;            /* speed of light (> 0; 1 in normalized units)                 */
   double eps0;         /* vacuum permittivity (> 0; 1 in normalized units)           */
   uint32_t flags;      /* PSATD_FLAG_*                                                */
@@ -150,6 +156,53 @@ psatd_status psatd_destroy(psatd_plan_t plan);
 
 const char* psatd_status_string(psatd_status status);
 const char* psatd_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Guard-cell domain decomposition (Sec. II.A: the pseudo-spectral solvers of
+ * PXR split the domain into subdomains whose guard regions copy the adjacent
+ * subdomains, and solve each with local FFTs; the price is a truncation error
+ * that falls with the guard width for finite stencil orders p).
+ *
+ * A periodic global grid is split into parts[0] x parts[1] x parts[2] boxes of
+ * n[a] / parts[a] cells.  Each box, extended by guard[a] cells on both sides of
+ * every split axis (parts[a] > 1), is one periodic patch of an internal batched
+ * plan; its side box + 2 guard must be an even 2^a 3^b <= 4096.  Each step of
+ * psatd_domain_push: fill every patch, interior and guards, from the global
+ * fields at the periodic global positions (the guard exchange: copies of the
+ * neighbours' current values; sources likewise), advance all patches one step,
+ * and write each patch's interior back to its box of the global E and B.
+ * The guard cells introduce the truncation error; use order p > 0 with
+ * PSATD_FLAG_CENTERED_STENCIL for operators that stay local.
+ * ------------------------------------------------------------------------- */
+typedef struct psatd_domain_s* psatd_domain_t;
+
+typedef struct {
+  int32_t ndim;     /* 2: (x, z) plane, n[1] = parts[1] = 1;  3: (x, y, z)         */
+  int32_t reserved0;
+  int64_t n[3];     /* global nx, ny, nz (periodic)                                */
+  int32_t parts[3]; /* boxes per axis, each dividing n[a]                          */
+  int32_t guard[3]; /* guard cells per side on split axes (ignored where parts = 1) */
+  double d[3];      /* dx, dy, dz > 0                                              */
+  double dt;        /* > 0                                                         */
+} psatd_domain_desc;
+
+/* Build the decomposition and its internal plan (same config; the config's
+ * flags apply to it).  Allocates the local patches (the plan's component count
+ * x patches x local cells) and the plan's workspace.  Errors as psatd_plan;
+ * PSATD_ERR_UNSUPPORTED_SIZE if a local side is not a supported length. */
+psatd_status psatd_domain_create(const psatd_config* config, const psatd_domain_desc* domain,
+                                 int32_t device, psatd_domain_t* out);
+
+/* Number of local patches and their shape (nx, ny, nz incl. guards). */
+psatd_status psatd_domain_local_shape(psatd_domain_t domain, int64_t* npatch, int64_t local_n[3]);
+
+/* Advance the global fields by nsteps decomposed steps on hip_stream (E, B of
+ * the global grid in place; J, rho as in psatd_push; nsteps > 1 in vacuum
+ * only).  Asynchronous, no allocation. */
+psatd_status psatd_domain_push(psatd_domain_t domain, const psatd_fields* global_fields,
+                               int32_t nsteps, void* hip_stream);
+
+psatd_status psatd_domain_destroy(psatd_domain_t domain);
 
 #ifdef __cplusplus
 }

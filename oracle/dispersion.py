@@ -93,14 +93,48 @@ def fornberg_staggered(p: int):
     return weights
 
 
-def modified_k(k, dx, p: int):
-    """k_p = sum_l C_l^p (2/dx) sin((2l-1) k dx/2); p = 0 returns k (infinite order)."""
+def fornberg_centered(p: int):
+    """Centered (collocated) first-derivative weights a_1..a_{p/2} (exact rationals).
+
+    f'(0) ~ sum_l a_l [f(l h) - f(-l h)] / h on the integer nodes -p/2..p/2.
+    a_l is the derivative at 0 of the Lagrange basis polynomial of node l;
+    one factor of that polynomial is x / l, so L_l'(0) is the product of the
+    remaining factors at 0, divided by l.
+    """
+    if p < 2 or p % 2:
+        raise ValueError("p must be even and >= 2")
+    half = p // 2
+    nodes = [Fraction(j) for j in range(-half, half + 1)]
+    weights = []
+    for l in range(1, half + 1):
+        xj = Fraction(l)
+        prod = Fraction(1)
+        for xn in nodes:
+            if xn != xj and xn != 0:
+                prod *= (0 - xn) / (xj - xn)
+        weights.append(prod / xj)
+    return weights
+
+
+def modified_k(k, dx, p: int, stencil: str = "staggered"):
+    """Wavenumber of the order-p first-derivative stencil; p = 0 returns k.
+
+    staggered (Table 1 caption):  k_p = sum_l C_l (2/dx) sin((2l-1) k dx/2)
+    centered (collocated nodes):  k_p = sum_l a_l (2/dx) sin(l k dx), which
+                                  vanishes smoothly at the Nyquist wavenumber.
+    """
     k = np.asarray(k, dtype=np.float64)
     if p == 0:
         return k.copy()
     out = np.zeros_like(k)
-    for l, cl in enumerate(fornberg_staggered(p), start=1):
-        out += float(cl) * (2.0 / dx) * np.sin((2 * l - 1) * k * dx / 2.0)
+    if stencil == "staggered":
+        for l, cl in enumerate(fornberg_staggered(p), start=1):
+            out += float(cl) * (2.0 / dx) * np.sin((2 * l - 1) * k * dx / 2.0)
+    elif stencil == "centered":
+        for l, al in enumerate(fornberg_centered(p), start=1):
+            out += float(al) * (2.0 / dx) * np.sin(l * k * dx)
+    else:
+        raise ValueError(f"unknown stencil {stencil!r}")
     return out
 
 

@@ -61,40 +61,41 @@ _WORKERS = os.cpu_count() or 1
 
 
 # ---------------------------------------------------------------- k tables
-def ktable(n: int, d: float, order: int = 0) -> np.ndarray:
+def ktable(n: int, d: float, order: int = 0, stencil: str = "staggered") -> np.ndarray:
     """Lattice wavenumbers of a full (c2c) axis in fftfreq order, Nyquist -> 0.
 
     ``order`` = p > 0 replaces k by the order-p modified wavevector k_p
-    (Sec. III.B; Table 1 caption); 0 keeps the exact k.
+    (Sec. III.B; Table 1 caption) of the ``stencil`` ("staggered", the
+    default, or "centered"); 0 keeps the exact k.
     """
     m = np.arange(n)
     m = np.where(m < (n + 1) // 2, m, m - n).astype(np.float64)
     k = 2.0 * np.pi * m / (n * d)
     if order:
-        k = modified_k(k, d, order)
+        k = modified_k(k, d, order, stencil)
     if n % 2 == 0:
         k[n // 2] = 0.0
     return k
 
 
-def rktable(n: int, d: float, order: int = 0) -> np.ndarray:
+def rktable(n: int, d: float, order: int = 0, stencil: str = "staggered") -> np.ndarray:
     """Wavenumbers of the halved r2c axis (indices 0..n/2), Nyquist -> 0."""
-    return ktable(n, d, order)[: n // 2 + 1]
+    return ktable(n, d, order, stencil)[: n // 2 + 1]
 
 
-def _kvectors(shape, d, transform, order=0):
+def _kvectors(shape, d, transform, order=0, stencil="staggered"):
     """Broadcastable (kx, ky, kz) for spectra of arrays shaped [z][x] or [z][y][x]."""
     kx_fn = rktable if transform == "r2c" else ktable
     if len(shape) == 2:
         nz, nx = shape
-        kx = kx_fn(nx, d[0], order)[None, :]
-        kz = ktable(nz, d[2], order)[:, None]
+        kx = kx_fn(nx, d[0], order, stencil)[None, :]
+        kz = ktable(nz, d[2], order, stencil)[:, None]
         ky = np.zeros((1, 1))
     else:
         nz, ny, nx = shape
-        kx = kx_fn(nx, d[0], order)[None, None, :]
-        ky = ktable(ny, d[1], order)[None, :, None]
-        kz = ktable(nz, d[2], order)[:, None, None]
+        kx = kx_fn(nx, d[0], order, stencil)[None, None, :]
+        ky = ktable(ny, d[1], order, stencil)[None, :, None]
+        kz = ktable(nz, d[2], order, stencil)[:, None, None]
     return kx, ky, kz
 
 
@@ -217,17 +218,17 @@ def inverse(F, shape, transform="r2c", workers=None):
 
 # ---------------------------------------------------------------- the step
 def psatd_step(E, B, J=None, rho_old=None, rho_new=None, *, d, dt, c=1.0, eps0=1.0,
-               form="rho", transform="r2c", order=0, workers=None):
+               form="rho", transform="r2c", order=0, stencil="staggered", workers=None):
     """One PSATD step on a periodic grid.
 
     E, B: three real arrays each ([z][x] or [z][y][x]); J: three arrays or None;
     rho_old, rho_new: arrays or None.  ``d`` = (dx, dy, dz) (dy unused in 2D).
-    ``order`` selects the order-p wavevector (0: exact k).
+    ``order`` selects the order-p wavevector (0: exact k) of ``stencil``.
     Steps, in the method's order: forward FFT of every input, the per-mode
     update of :func:`update_modes`, inverse FFT of E and B.
     """
     shape = E[0].shape
-    k = _kvectors(shape, d, transform, order)
+    k = _kvectors(shape, d, transform, order, stencil)
     Ek = [forward(f, transform, workers) for f in E]
     Bk = [forward(f, transform, workers) for f in B]
     Jk = [forward(f, transform, workers) for f in J] if J is not None else None
@@ -240,8 +241,8 @@ def psatd_step(E, B, J=None, rho_old=None, rho_new=None, *, d, dt, c=1.0, eps0=1
 
 
 def psatd_run(E, B, steps, *, d, dt, schedule=None, c=1.0, eps0=1.0, form="rho",
-              transform="r2c", order=0, source_dtype=np.float64, workers=None,
-              callback=None):
+              transform="r2c", order=0, stencil="staggered", source_dtype=np.float64,
+              workers=None, callback=None):
     """``steps`` successive steps; sources of step n come from ``schedule.sources(n)``.
 
     ``source_dtype`` rounds the sources before use (float32 reproduces what an
@@ -258,7 +259,7 @@ def psatd_run(E, B, steps, *, d, dt, schedule=None, c=1.0, eps0=1.0, form="rho",
         else:
             J = ro = rn = None
         E, B = psatd_step(E, B, J, ro, rn, d=d, dt=dt, c=c, eps0=eps0, form=form,
-                          transform=transform, order=order, workers=workers)
+                          transform=transform, order=order, stencil=stencil, workers=workers)
         if callback is not None:
             callback(n, E, B)
     return E, B

@@ -6,6 +6,7 @@ fallback: if the library is not built, loading it raises.
 """
 
 from ._binding import (  # noqa: F401
+    Domain,
     EXPORTED_SYMBOLS,
     LIBRARY_PATH,
     Patch,

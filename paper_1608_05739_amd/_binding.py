@@ -28,11 +28,13 @@ FLAG_AUTOTUNE = 0x1
 FLAG_GRAPH = 0x2
 FLAG_NO_WORKSPACE = 0x4
 FLAG_GENERIC_KERNELS = 0x8
+FLAG_CENTERED_STENCIL = 0x10
 
 EXPORTED_SYMBOLS = (
     "psatd_plan", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
     "psatd_push_profiled", "psatd_pass_count", "psatd_pass_name", "psatd_pass_bytes",
     "psatd_plan_info", "psatd_destroy", "psatd_status_string", "psatd_last_error",
+    "psatd_domain_create", "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
 )
 
 
@@ -53,6 +55,13 @@ class Fields(ctypes.Structure):
     _fields_ = [("E", ctypes.c_void_p * 3), ("B", ctypes.c_void_p * 3),
                 ("J", ctypes.c_void_p * 3), ("rho_old", ctypes.c_void_p),
                 ("rho_new", ctypes.c_void_p)]
+
+
+class DomainDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("parts", ctypes.c_int32 * 3),
+                ("guard", ctypes.c_int32 * 3), ("d", ctypes.c_double * 3),
+                ("dt", ctypes.c_double)]
 
 
 class PsatdError(RuntimeError):
@@ -93,9 +102,16 @@ def load_library(path: Optional[str] = None):
     lib.psatd_status_string.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     lib.psatd_last_error.restype = ctypes.c_char_p
+    lib.psatd_domain_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(DomainDesc), i32,
+                                        ctypes.POINTER(vp)]
+    lib.psatd_domain_local_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.c_int64 * 3]
+    lib.psatd_domain_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
+    lib.psatd_domain_destroy.argtypes = [vp]
     for name in ("psatd_plan", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
                  "psatd_push_profiled", "psatd_pass_count", "psatd_pass_bytes",
-                 "psatd_plan_info", "psatd_destroy"):
+                 "psatd_plan_info", "psatd_destroy", "psatd_domain_create",
+                 "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -136,6 +152,51 @@ def as_patch(p) -> Patch:
                  getattr(p, "offset", None))
 
 
+def make_config(precision="fp32", source_mode="vacuum", path="fused", order=0, c=1.0, eps0=1.0,
+                *, autotune=False, graph=False, allocate_workspace=True, generic_kernels=False,
+                centered_stencil=False) -> Config:
+    cfg = Config()
+    cfg.precision = PRECISION[precision]
+    cfg.source_mode = SOURCE_MODE[source_mode]
+    cfg.path = PATH[path]
+    cfg.order = int(order)
+    cfg.c = float(c)
+    cfg.eps0 = float(eps0)
+    cfg.flags = ((FLAG_AUTOTUNE if autotune else 0) | (FLAG_GRAPH if graph else 0)
+                 | (0 if allocate_workspace else FLAG_NO_WORKSPACE)
+                 | (FLAG_GENERIC_KERNELS if generic_kernels else 0)
+                 | (FLAG_CENTERED_STENCIL if centered_stencil else 0))
+    return cfg
+
+
+def _field_struct(E, B, J, rho_old, rho_new, want_dtype, min_elements):
+    import torch
+
+    def ptr(t, name):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != want_dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {want_dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() < min_elements:
+            raise ValueError(f"{name} holds {t.numel()} elements < {min_elements}")
+        return t.data_ptr()
+
+    f = Fields()
+    for i in range(3):
+        f.E[i] = ptr(E[i], f"E[{i}]")
+        f.B[i] = ptr(B[i], f"B[{i}]")
+        f.J[i] = ptr(J[i], f"J[{i}]") if J is not None else None
+    f.rho_old = ptr(rho_old, "rho_old")
+    f.rho_new = ptr(rho_new, "rho_new")
+    return f
+
+
 class Plan:
     """A PSATD plan over one or more periodic patches on one HIP device.
 
@@ -145,7 +206,8 @@ class Plan:
 
     def __init__(self, patches: Sequence, *, precision="fp32", source_mode="vacuum",
                  path="fused", order=0, c=1.0, eps0=1.0, autotune=False, graph=False,
-                 device=0, allocate_workspace=True, generic_kernels=False):
+                 device=0, allocate_workspace=True, generic_kernels=False,
+                 centered_stencil=False):
         self._lib = load_library()
         self._plan = None
         ps = [as_patch(p) for p in patches]
@@ -170,16 +232,9 @@ class Plan:
             descs[i].d = (ctypes.c_double * 3)(*[float(v) for v in p.d])
             descs[i].dt = float(p.dt)
             descs[i].offset = self.offsets[i]
-        cfg = Config()
-        cfg.precision = PRECISION[precision]
-        cfg.source_mode = SOURCE_MODE[source_mode]
-        cfg.path = PATH[path]
-        cfg.order = int(order)
-        cfg.c = float(c)
-        cfg.eps0 = float(eps0)
-        cfg.flags = ((FLAG_AUTOTUNE if autotune else 0) | (FLAG_GRAPH if graph else 0)
-                     | (0 if allocate_workspace else FLAG_NO_WORKSPACE)
-                     | (FLAG_GENERIC_KERNELS if generic_kernels else 0))
+        cfg = make_config(precision, source_mode, path, order, c, eps0, autotune=autotune,
+                          graph=graph, allocate_workspace=allocate_workspace,
+                          generic_kernels=generic_kernels, centered_stencil=centered_stencil)
         handle = ctypes.c_void_p()
         _check(self._lib, self._lib.psatd_plan(ctypes.byref(cfg), descs, len(ps), int(device),
                                                 ctypes.byref(handle)))
@@ -228,30 +283,7 @@ class Plan:
         import torch
 
         want = torch.float32 if self.precision == "fp32" else torch.float64
-
-        def ptr(t, name):
-            if t is None:
-                return None
-            if not isinstance(t, torch.Tensor):
-                raise TypeError(f"{name} must be a torch tensor")
-            if not t.is_cuda:
-                raise ValueError(f"{name} must be a device tensor")
-            if t.dtype != want:
-                raise TypeError(f"{name} has dtype {t.dtype}, plan expects {want}")
-            if not t.is_contiguous():
-                raise ValueError(f"{name} must be contiguous")
-            if t.numel() < self.total_elements:
-                raise ValueError(f"{name} holds {t.numel()} elements < {self.total_elements}")
-            return t.data_ptr()
-
-        f = Fields()
-        for i in range(3):
-            f.E[i] = ptr(E[i], f"E[{i}]")
-            f.B[i] = ptr(B[i], f"B[{i}]")
-            f.J[i] = ptr(J[i], f"J[{i}]") if J is not None else None
-        f.rho_old = ptr(rho_old, "rho_old")
-        f.rho_new = ptr(rho_new, "rho_new")
-        return f
+        return _field_struct(E, B, J, rho_old, rho_new, want, self.total_elements)
 
     @staticmethod
     def _stream(stream):
@@ -291,3 +323,60 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Domain:
+    """Guard-cell domain decomposition of a periodic grid (Sec. II.A).
+
+    ``n`` = (nx, ny, nz) global (ny = 1 in 2D), ``parts`` boxes per axis,
+    ``guard`` cells per side on split axes.  :meth:`push` advances global E, B
+    (flat tensors of nx*ny*nz elements) through the decomposed step.
+    """
+
+    def __init__(self, ndim, n, parts, guard, d, dt, *, precision="fp32", source_mode="vacuum",
+                 path="fused", order=0, c=1.0, eps0=1.0, centered_stencil=False, graph=False,
+                 device=0):
+        self._lib = load_library()
+        self._dom = None
+        desc = DomainDesc()
+        desc.ndim = int(ndim)
+        desc.n = (ctypes.c_int64 * 3)(*[int(v) for v in n])
+        desc.parts = (ctypes.c_int32 * 3)(*[int(v) for v in parts])
+        desc.guard = (ctypes.c_int32 * 3)(*[int(v) for v in guard])
+        desc.d = (ctypes.c_double * 3)(*[float(v) for v in d])
+        desc.dt = float(dt)
+        cfg = make_config(precision, source_mode, path, order, c, eps0, graph=graph,
+                          centered_stencil=centered_stencil)
+        handle = ctypes.c_void_p()
+        _check(self._lib, self._lib.psatd_domain_create(ctypes.byref(cfg), ctypes.byref(desc),
+                                                         int(device), ctypes.byref(handle)))
+        self._dom = handle
+        self.precision = precision
+        self.cells = int(n[0]) * int(n[1]) * int(n[2])
+
+    @property
+    def local_shape(self):
+        npatch = ctypes.c_int64()
+        ln = (ctypes.c_int64 * 3)()
+        _check(self._lib, self._lib.psatd_domain_local_shape(self._dom, ctypes.byref(npatch), ln))
+        return npatch.value, tuple(ln)
+
+    def push(self, E, B, J=None, rho_old=None, rho_new=None, steps=1, stream=None):
+        import torch
+
+        want = torch.float32 if self.precision == "fp32" else torch.float64
+        f = _field_struct(E, B, J, rho_old, rho_new, want, self.cells)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self._lib, self._lib.psatd_domain_push(self._dom, ctypes.byref(f), int(steps),
+                                                       ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if self._dom is not None:
+            self._lib.psatd_domain_destroy(self._dom)
+            self._dom = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -81,6 +81,20 @@ std::vector<double> fornberg_staggered(int p) {
   return w;
 }
 
+// Centered first-derivative weights a_1..a_{p/2} on the integer nodes
+// -p/2..p/2: a_l = (-1)^(l+1) (m!)^2 / ((m-l)! (m+l)! l), m = p/2, written as
+// a running product so that no factorial is formed.
+std::vector<double> fornberg_centered(int p) {
+  const int m = p / 2;
+  std::vector<double> w;
+  double ratio = 1.0;  // (m!)^2 / ((m-l)! (m+l)!)
+  for (int l = 1; l <= m; ++l) {
+    ratio *= static_cast<double>(m - l + 1) / static_cast<double>(m + l);
+    w.push_back(((l % 2) ? 1.0 : -1.0) * ratio / l);
+  }
+  return w;
+}
+
 struct DeviceGuard {
   int prev = -1;
   bool ok = false;
@@ -119,6 +133,8 @@ const char* line_pass_name(int kind) {
 }
 
 }  // namespace
+
+psatd_status set_last_error(psatd_status s, const std::string& msg) { return fail(s, msg); }
 
 struct psatd_plan_s {
   psatd_config cfg{};
@@ -184,7 +200,7 @@ psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, 
   if (!(cfg->eps0 > 0.0) || !std::isfinite(cfg->eps0))
     return fail(PSATD_ERR_INVALID_ARG, "eps0 must be > 0");
   if (cfg->flags & ~(PSATD_FLAG_AUTOTUNE | PSATD_FLAG_GRAPH | PSATD_FLAG_NO_WORKSPACE |
-                     PSATD_FLAG_GENERIC_KERNELS))
+                     PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_CENTERED_STENCIL))
     return fail(PSATD_ERR_INVALID_ARG, "unknown flag bits");
   const int ndim = patches[0].ndim;
   std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -652,7 +668,8 @@ psatd_status build_plan(psatd_plan_s* plan) {
       if (!tw_off.count(L)) tw_off[L] = take(sizeof(double2) * L);
   }
   std::vector<double> fw;
-  if (cfg.order > 0) fw = fornberg_staggered(cfg.order);
+  const int centered = (cfg.flags & PSATD_FLAG_CENTERED_STENCIL) ? 1 : 0;
+  if (cfg.order > 0) fw = centered ? fornberg_centered(cfg.order) : fornberg_staggered(cfg.order);
   // The device sincos is accurate for |theta/2| <= kSincosMax; bound |k| per
   // axis by pi/d (exact k) or (2/d) sum |C_l| (order p).
   {
@@ -722,15 +739,15 @@ psatd_status build_plan(psatd_plan_s* plan) {
     fill(P.fz, P.nz, kMaxRadixZ);
     plan->host_patches.push_back(P);
 
-    e = launch_ktable(const_cast<double*>(P.kx), P.nx, d.d[0], P.mx, 1, d_fw, nfw, nullptr);
+    e = launch_ktable(const_cast<double*>(P.kx), P.nx, d.d[0], P.mx, 1, d_fw, nfw, centered, nullptr);
     if (e == hipSuccess && plan->ndim == 3)
-      e = launch_ktable(const_cast<double*>(P.ky), P.ny, d.d[1], P.ny, 0, d_fw, nfw, nullptr);
+      e = launch_ktable(const_cast<double*>(P.ky), P.ny, d.d[1], P.ny, 0, d_fw, nfw, centered, nullptr);
     if (e == hipSuccess && plan->ndim == 2) {
       const double zero = 0.0;
       e = hipMemcpy(const_cast<double*>(P.ky), &zero, sizeof(double), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess)
-      e = launch_ktable(const_cast<double*>(P.kz), P.nz, d.d[2], P.nz, 0, d_fw, nfw, nullptr);
+      e = launch_ktable(const_cast<double*>(P.kz), P.nz, d.d[2], P.nz, 0, d_fw, nfw, centered, nullptr);
     if (e == hipSuccess)
       e = launch_twiddles(const_cast<double2*>(P.post), P.nx, P.mx, nullptr);
     if (e != hipSuccess) return hip_fail(e, "k tables");

@@ -404,11 +404,12 @@ __global__ void twiddle_kernel(double2* tw, int n, int count) {
 
 // k_j = 2 pi m_j / (n d) in fftfreq order, the Nyquist index (even n) -> 0.
 // packed_x: entries j = 0..count-1 of the halved x axis, entry 0 standing for
-// both the DC and the Nyquist columns (k = 0 for both).  With Fornberg weights
-// C_l (nf = p/2 of them) the order-p wavevector
-// k_p = sum_l C_l (2/d) sin((2l - 1) k d / 2) replaces k.
+// both the DC and the Nyquist columns (k = 0 for both).  With stencil weights
+// w_l (nf = p/2 of them) the order-p wavevector replaces k:
+//   staggered  k_p = sum_l w_l (2/d) sin((2l - 1) k d / 2)
+//   centered   k_p = sum_l w_l (2/d) sin(l k d)
 __global__ void ktable_kernel(double* k, int n, double d, int count, int packed_x,
-                              const double* __restrict__ fornberg, int nf) {
+                              const double* __restrict__ fornberg, int nf, int centered) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= count) return;
   int m = (j < (n + 1) / 2) ? j : j - n;
@@ -418,7 +419,10 @@ __global__ void ktable_kernel(double* k, int n, double d, int count, int packed_
   double kv = kTwoPi * static_cast<double>(m) / (static_cast<double>(n) * d);
   if (nf > 0) {
     double acc = 0.0;
-    for (int l = 1; l <= nf; ++l) acc += fornberg[l - 1] * (2.0 / d) * sin((2 * l - 1) * kv * d * 0.5);
+    for (int l = 1; l <= nf; ++l) {
+      const double arg = centered ? l * kv * d : (2 * l - 1) * kv * d * 0.5;
+      acc += fornberg[l - 1] * (2.0 / d) * sin(arg);
+    }
     kv = acc;
   }
   if (nyquist || (packed_x && j == 0)) kv = 0.0;
@@ -551,10 +555,11 @@ hipError_t launch_twiddles(double2* tw, int n, int count, hipStream_t stream) {
 }
 
 hipError_t launch_ktable(double* k, int n, double d, int count, int packed_x,
-                         const double* fornberg, int nfornberg, hipStream_t stream) {
+                         const double* fornberg, int nfornberg, int centered,
+                         hipStream_t stream) {
   const int b = 256;
   hipLaunchKernelGGL(ktable_kernel, dim3((count + b - 1) / b), dim3(b), 0, stream, k, n, d, count,
-                     packed_x, fornberg, nfornberg);
+                     packed_x, fornberg, nfornberg, centered);
   return hipGetLastError();
 }
 

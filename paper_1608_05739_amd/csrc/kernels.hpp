@@ -48,7 +48,8 @@ hipError_t launch_update(int precision, int src, const LaunchShape& sh, hipStrea
 // FP64 plan tables.
 hipError_t launch_twiddles(double2* tw, int n, int count, hipStream_t stream);
 hipError_t launch_ktable(double* k, int n, double d, int count, int packed_x,
-                         const double* fornberg, int nfornberg, hipStream_t stream);
+                         const double* fornberg, int nfornberg, int centered,
+                         hipStream_t stream);
 
 // Raise the dynamic-LDS limit of every kernel instantiation (once per process).
 hipError_t configure_kernel_attributes();

@@ -109,3 +109,29 @@ def test_null_arguments(lib):
 def test_package_fails_loudly_without_library(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         b.load_library(str(tmp_path / "missing.so"))
+
+
+def _dom(n=(128, 1, 128), parts=(2, 1, 2), guard=(16, 0, 16), ndim=2):
+    dd = b.DomainDesc()
+    dd.ndim = ndim
+    dd.n = (ctypes.c_int64 * 3)(*n)
+    dd.parts = (ctypes.c_int32 * 3)(*parts)
+    dd.guard = (ctypes.c_int32 * 3)(*guard)
+    dd.d = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    dd.dt = 0.05
+    return dd
+
+
+@pytest.mark.parametrize("dom,expect", [
+    (_dom(guard=(5, 0, 16)), -2),            # 64 + 2 * 5 = 74 = 2 * 37: unsupported length
+    (_dom(parts=(3, 1, 2)), -1),             # 128 does not split into 3 equal boxes
+    (_dom(guard=(-1, 0, 16)), -1),           # negative guard
+    (_dom(n=(128, 2, 128)), -1),             # 2D with ny != 1
+    (_dom(ndim=4), -1),
+])
+def test_domain_validation_on_host(lib, dom, expect):
+    h = ctypes.c_void_p()
+    st = lib.psatd_domain_create(ctypes.byref(_cfg()), ctypes.byref(dom), 0, ctypes.byref(h))
+    assert st == expect
+    assert h.value is None
+    assert lib.psatd_last_error().decode()

@@ -90,7 +90,7 @@ MUTANTS = {
     "cross index slip": ("_cross", lambda a, b: (a[1] * b[2] - a[2] * b[1],
                                                  a[2] * b[0] - a[0] * b[2],
                                                  a[0] * b[2] - a[1] * b[0])),
-    "Nyquist kept": ("ktable", lambda n, d, order=0: 2 * np.pi * np.fft.fftfreq(n, d=d)),
+    "Nyquist kept": ("ktable", lambda n, d, order=0, stencil="staggered": 2 * np.pi * np.fft.fftfreq(n, d=d)),
 }
 
 
