@@ -651,7 +651,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
     tb += (bytes + 255) / 256 * 256;
     return o;
   };
-  struct PT { size_t kx, ky, kz, post; };
+  struct PT { size_t kx, ky, kz, kz_b, post; };
   std::vector<PT> pt;
   for (const psatd_patch_desc& d : plan->desc) {
     const int nx = static_cast<int>(d.n[0]);
@@ -662,6 +662,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
     t.kx = take(sizeof(double) * mx);
     t.ky = take(sizeof(double) * ny);
     t.kz = take(sizeof(double) * nz);
+    t.kz_b = take(sizeof(double) * nz);
     t.post = take(sizeof(double2) * mx);
     pt.push_back(t);
     for (int L : {mx, ny, nz})
@@ -726,6 +727,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
     P.kx = reinterpret_cast<const double*>(T + pt[i].kx);
     P.ky = reinterpret_cast<const double*>(T + pt[i].ky);
     P.kz = reinterpret_cast<const double*>(T + pt[i].kz);
+    P.kz_b = reinterpret_cast<const double*>(T + pt[i].kz_b);
     P.post = reinterpret_cast<const double2*>(T + pt[i].post);
     auto fill = [&](FFTPlanDev& f, int L, int max_radix) {
       const std::vector<int> r = radix_plan(L, max_radix);
@@ -751,6 +753,18 @@ psatd_status build_plan(psatd_plan_s* plan) {
     if (e == hipSuccess)
       e = launch_twiddles(const_cast<double2*>(P.post), P.nx, P.mx, nullptr);
     if (e != hipSuccess) return hip_fail(e, "k tables");
+    if (P.nz == fast2d::kNZfast) {
+      // mode order of the specialized z pass (see PatchDev::kz_b)
+      std::vector<double> kz(P.nz), kzb(P.nz);
+      e = hipMemcpy(kz.data(), P.kz, sizeof(double) * P.nz, hipMemcpyDeviceToHost);
+      for (int q = 0; q < 8; ++q)
+        for (int k2 = 0; k2 < 8; ++k2)
+          for (int j = 0; j < 64; ++j) kzb[64 * k2 + j + 512 * q] = kz[8 * j + k2 + 512 * q];
+      if (e == hipSuccess)
+        e = hipMemcpy(const_cast<double*>(P.kz_b), kzb.data(), sizeof(double) * P.nz,
+                      hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "kz table (z pass order)");
+    }
   }
   // 3D: a second block of the same size for the z passes (see PatchDev::off_z)
   for (PatchDev& P : plan->host_patches) P.off_z = plan->ndim == 3 ? spec_off + P.off_spec : P.off_spec;

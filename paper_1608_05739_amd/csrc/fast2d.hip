@@ -336,61 +336,129 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 }
 
 // ------------------------------------------------------------------ P2
-// Fused z pass on one column kx (4096 modes) per workgroup of 512 threads.
-// Thread t = 8 j + k2 works on the 512-point transform of group k2 over
-// z1 (or k1) and holds entries j + 64 q, q < 8.  LDS exchanges use two FP64
-// buffers laid out [e][k2] (element e of group k2 at 8 e + k2): the eight
-// lanes that the LDS serves together share j and differ in k2, so every
-// exchange is bank-conflict free.
-// The twiddle bases are read from the table inside each call, after a
-// barrier: otherwise the compiler would keep the powers of the (identical)
-// bases of every call live across the whole kernel.
+// Fused z pass on one column kx (4096 modes) per workgroup of 512 threads,
+// run as eight 512-point transforms (group k2 over z1 or k1), each with three
+// radix-8 stages.  Two thread mappings:
+//   A (global memory): thread t = 8 j + k2 holds elements j + 64 q of group k2,
+//     i.e. column positions t + 512 q: coalesced loads and stores;
+//   B (transform and update): wave w = k2 holds group k2, lane j its elements
+//     j + 64 q; the mode index of element j + 64 q of group k2 is
+//     8 (j + 64 q) + k2.
+// A forward transform runs stage 1 in A, hands over to B through LDS (the one
+// workgroup barrier) and runs stages 2 and 3 in B with a wave-private
+// exchange.  The inverse is the adjoint of the forward (stages in reverse
+// order, exchanges transposed, butterflies and twiddles conjugated): stages 3
+// and 2 in B, hand-over, stage 1 in A.  Waves meet once per transform.
+// LDS: two transition buffers used alternately, so that the writes of one
+// hand-over never meet the reads of the previous one (a barrier always lies
+// between two uses of the same buffer); a wave's private exchange uses its own
+// group's region of the current buffer.  Element e of group k2 lives at
+// 513 k2 + e: the eight lanes that the LDS serves together then hit
+// consecutive slots in every access below, and every address is a per-thread
+// base plus a compile-time offset.
+constexpr int kGroupStride = 513;
+constexpr int kZBuf = kGroupStride * 7 + 512;  // double2 per transition buffer
+
 template <int SIGN>
-__device__ __forceinline__ void fft512_group(double2 (&v)[8], double2* bufA, double2* bufB, int j,
-                                             int k2, const double2* __restrict__ tw4096) {
-  // stage 1: radix 8, Ns = 1
-  DFT<8, SIGN>::run(v);
+__device__ __forceinline__ void twiddle8(double2 (&v)[8], double2 w) {
+  if constexpr (SIGN > 0) w.y = -w.y;
+  double2 wq = w;
+  v[1] = cmul(v[1], w);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) bufA[(8 * j + q) * 8 + k2] = v[q];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = bufA[(j + 64 * q) * 8 + k2];
-  // stage 2: radix 8, Ns = 8, k = j mod 8, w = exp(SIGN 2 pi i k / 64)
-  {
-    double2 w = tw4096[64 * (j & 7)];
-    if constexpr (SIGN > 0) w.y = -w.y;
-    double2 wq = w;
-    v[1] = cmul(v[1], w);
-#pragma unroll
-    for (int q = 2; q < 8; ++q) {
-      wq = cmul(wq, w);
-      v[q] = cmul(v[q], wq);
-    }
+  for (int q = 2; q < 8; ++q) {
+    wq = cmul(wq, w);
+    v[q] = cmul(v[q], wq);
   }
-  DFT<8, SIGN>::run(v);
-  const int k = j & 7;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) bufB[((j - k) * 8 + k + 8 * q) * 8 + k2] = v[q];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = bufB[(j + 64 * q) * 8 + k2];
-  // stage 3: radix 8, Ns = 64, k = j, w = exp(SIGN 2 pi i j / 512)
-  {
-    double2 w = tw4096[8 * j];
-    if constexpr (SIGN > 0) w.y = -w.y;
-    double2 wq = w;
-    v[1] = cmul(v[1], w);
-#pragma unroll
-    for (int q = 2; q < 8; ++q) {
-      wq = cmul(wq, w);
-      v[q] = cmul(v[q], wq);
-    }
-  }
-  DFT<8, SIGN>::run(v);
 }
 
-// Loads of one component column into FP32 registers (modes t + 512 q): a
-// uniform base per q plus one 32-bit lane offset (SGPR-base addressing).
+// Thread indices of both mappings and the LDS bases of the exchanges.
+struct ZIdx {
+  int tA, jA, k2A;  // mapping A
+  int tB, jB, k2B;  // mapping B (tB = 64 k2B + jB = threadIdx.x)
+  int baseA;        // element 8 jA of group k2A       (+ q)
+  int baseB1;       // element jB of group k2B         (+ 64 q)
+  int baseB2;       // element 8 (jB - k) + k, k = jB mod 8, of group k2B (+ 8 q)
+};
+
+__device__ __forceinline__ ZIdx make_zidx() {
+  ZIdx x;
+  x.tA = threadIdx.x;
+  x.jA = x.tA >> 3;
+  x.k2A = x.tA & 7;
+  x.tB = threadIdx.x;
+  x.jB = x.tB & 63;
+  x.k2B = x.tB >> 6;
+  const int k = x.jB & 7;
+  x.baseA = kGroupStride * x.k2A + 8 * x.jA;
+  x.baseB1 = kGroupStride * x.k2B + x.jB;
+  x.baseB2 = kGroupStride * x.k2B + 8 * (x.jB - k) + k;
+  return x;
+}
+
+// Forward: v holds elements jA + 64 q of group k2A (mapping A) on entry and
+// transform outputs jB + 64 q of group k2B (mapping B) on exit.  The twiddle
+// bases are read from the table inside each call, after a barrier: otherwise
+// the compiler would keep the powers of the (identical) bases of every call
+// live across the whole kernel.
+__device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx& x,
+                                       const double2* __restrict__ tw4096) {
+  DFT<8, -1>::run(v);  // stage 1 (Ns = 1), mapping A; outputs 8 j + q
+  double2* wa = buf + x.baseA;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wa[q] = v[q];
+  __syncthreads();
+  double2* b1 = buf + x.baseB1;
+  double2* b2 = buf + x.baseB2;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = b1[64 * q];
+  // stage 2: Ns = 8, k = j mod 8, w = exp(-2 pi i k / 64); outputs 8 (j - k) + k + 8 q
+  twiddle8<-1>(v, tw4096[64 * (x.jB & 7)]);
+  DFT<8, -1>::run(v);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b2[8 * q] = v[q];
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = b1[64 * q];
+  // stage 3: Ns = 64, k = j, w = exp(-2 pi i j / 512); outputs j + 64 q
+  twiddle8<-1>(v, tw4096[8 * x.jB]);
+  DFT<8, -1>::run(v);
+}
+
+// conjugate twiddles applied after the butterflies (adjoint of twiddle8<-1>)
+__device__ __forceinline__ void twiddle8_adj(double2 (&v)[8], double2 w) {
+  twiddle8<1>(v, w);
+}
+
+// Inverse (unnormalized, the adjoint of fwd512): v holds elements jB + 64 q of
+// group k2B (mapping B) on entry and elements jA + 64 q of group k2A
+// (mapping A) on exit.
+__device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx& x,
+                                       const double2* __restrict__ tw4096) {
+  double2* b1 = buf + x.baseB1;
+  double2* b2 = buf + x.baseB2;
+  // adjoint of stage 3
+  DFT<8, 1>::run(v);
+  twiddle8_adj(v, tw4096[8 * x.jB]);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = b2[8 * q];
+  // adjoint of stage 2
+  DFT<8, 1>::run(v);
+  twiddle8_adj(v, tw4096[64 * (x.jB & 7)]);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
+  __syncthreads();
+  const double2* ra = buf + x.baseA;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = ra[q];
+  // adjoint of stage 1, mapping A
+  DFT<8, 1>::run(v);
+}
+
+// Loads of one component column into FP32 registers (mapping A, positions
+// t + 512 q): a uniform base per q plus one 32-bit lane offset.
 __device__ __forceinline__ void z_load(const float2* src, float2 (&raw)[8], int t) {
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -399,57 +467,29 @@ __device__ __forceinline__ void z_load(const float2* src, float2 (&raw)[8], int 
   }
 }
 
-// Forward transform of one loaded column into FP32 registers.
-__device__ __forceinline__ void z_fft_fwd(const float2 (&raw)[8], float2 (&dst)[8], double2* bufA,
-                                          double2* bufB, int j, int k2,
-                                          const double2* __restrict__ tw4096) {
-  double2 v[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = ld2(raw[q]);
-  fft512_group<-1>(v, bufA, bufB, j, k2, tw4096);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) dst[q] = st2(v[q]);
-  // keep the transform's temporaries apart from the update that follows
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-// Inverse transform of one component held in registers, twiddle W4096^(-z1 k2), store.
-__device__ __forceinline__ void z_inverse(const float2 (&src)[8], float2* dst, double2* bufA,
-                                          double2* bufB, int t, int j, int k2,
-                                          const double2* __restrict__ tw4096) {
-  double2 v[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = ld2(src[q]);
-  fft512_group<1>(v, bufA, bufB, j, k2, tw4096);
-  // W4096^(-z1 k2) for z1 = j + 64 q: start at W^(-j k2), step W^(-64 k2)
-  double2 tq = cconj(tw4096[(j * k2) & (kNZ - 1)]);
-  const double2 step = cconj(tw4096[(64 * k2) & (kNZ - 1)]);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    float2* __restrict__ bq = dst + 512 * q;
-    bq[t] = st2(cmul(v[q], tq));
-    if (q < 7) tq = cmul(tq, step);
-  }
-}
-
-// Per-column state of the z pass: thread t = 8 j + k2 holds the modes
-// kz index t + 512 q, q < 8, of column kx.
+// Per-column state of the z pass.  The transforms alternate between the two
+// transition buffers: `tr` counts them (uniform across the workgroup).
 struct ZCol {
   float2* col;       // workspace spectrum of column kx, component 0
   long long cs;      // component stride (complex elements)
   double kx, dt, c, c2, eps0, ie, scale;
-  const double* kz;  // kz table
+  const double* kzb; // kz in mapping-B order
   const double2* tw; // exp(-2 pi i m / 4096)
-  int t, j, k2;
-  double2* bufA;
-  double2* bufB;
+  ZIdx x;
+  double2* lds;      // two transition buffers of kZBuf double2
+  int tr;
 
+  __device__ __forceinline__ double2* next_buf() {
+    double2* b = lds + (tr & 1) * kZBuf;
+    ++tr;
+    return b;
+  }
   // The empty asm makes every read of kz opaque to the optimizer: the s and p
   // groups evaluate the same coefficients, and merging the two evaluations
   // would keep them live across the s group's inverse transforms.
   __device__ __forceinline__ double kz_of(int q) const {
-    const double* __restrict__ kzq = kz + 512 * q;
-    double v = kzq[t];
+    const double* __restrict__ kzq = kzb + 512 * q;
+    double v = kzq[x.tB];
     asm volatile("" : "+v"(v));
     return v;
   }
@@ -459,23 +499,40 @@ struct ZCol {
   __device__ __forceinline__ const float2* src(int comp) const { return col + comp * cs; }
   // Software pipeline: `pre` holds the loads issued one phase earlier.  Issue
   // the loads of `next` into `pre`, then transform the previous contents into
-  // `dst`, so that the HBM latency of the next input overlaps this transform
-  // and the update that follows it.
-  __device__ __forceinline__ void fwd(float2 (&pre)[8], const float2* next,
-                                      float2 (&dst)[8]) const {
-    float2 cur[8];
+  // `dst` (mapping B), so that the HBM latency of the next input overlaps this
+  // transform and the update that follows it.
+  __device__ __forceinline__ void fwd(float2 (&pre)[8], const float2* next, float2 (&dst)[8]) {
+    double2 v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) cur[q] = pre[q];
-    z_load(next, pre, t);
-    z_fft_fwd(cur, dst, bufA, bufB, j, k2, tw);
+    for (int q = 0; q < 8; ++q) v[q] = ld2(pre[q]);
+    z_load(next, pre, x.tA);
+    fwd512(v, next_buf(), x, tw);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dst[q] = st2(v[q]);
+    // keep the transform's temporaries apart from the update that follows
+    __builtin_amdgcn_sched_barrier(0);
   }
-  __device__ __forceinline__ void inv(int comp, const float2 (&src)[8]) const {
-    z_inverse(src, col + comp * cs, bufA, bufB, t, j, k2, tw);
+  // Inverse transform of one accumulator (mapping B), twiddle W4096^(-z1 k2)
+  // with z1 = jA + 64 q, store (mapping A).
+  __device__ __forceinline__ void inv(int comp, const float2 (&src_b)[8]) {
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = ld2(src_b[q]);
+    inv512(v, next_buf(), x, tw);
+    double2 tq = cconj(tw[(x.jA * x.k2A) & (kNZ - 1)]);
+    const double2 step = cconj(tw[(64 * x.k2A) & (kNZ - 1)]);
+    float2* dst = col + comp * cs;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float2* __restrict__ bq = dst + 512 * q;
+      bq[x.tA] = st2(cmul(v[q], tq));
+      if (q < 7) tq = cmul(tq, step);
+    }
   }
 };
 
 __device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* ws,
-                                          const Physics& ph, double2* bufA, double2* bufB) {
+                                          const Physics& ph, double2* lds, int tr) {
   ZCol z;
   z.col = reinterpret_cast<float2*>(ws) + P->off_spec + (long long)kxcol * kNZ;
   z.cs = P->comp_stride;
@@ -486,13 +543,11 @@ __device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* w
   z.eps0 = ph.eps0;
   z.ie = 1.0 / ph.eps0;
   z.scale = P->inv_n;
-  z.kz = P->kz;
+  z.kzb = P->kz_b;
   z.tw = P->fz.tw;
-  z.t = threadIdx.x;
-  z.k2 = z.t & 7;
-  z.j = z.t >> 3;
-  z.bufA = bufA;
-  z.bufB = bufB;
+  z.x = make_zidx();
+  z.lds = lds;
+  z.tr = tr;
   return z;
 }
 
@@ -512,7 +567,7 @@ __device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* w
 //   Ez: Ez' += C Ez,  By' += i S kx Ez
 // (p-pol with sources: z_ppol_sources.)
 template <int G, int SRC>
-__device__ __forceinline__ void z_group(const ZCol& z, float2 (&pre)[8], const float2* next) {
+__device__ __forceinline__ void z_group(ZCol& z, float2 (&pre)[8], const float2* next) {
   static_assert(G == 0 || SRC == kVacuum, "p-pol with sources has its own schedule");
   constexpr bool kSrc = SRC != kVacuum;
   constexpr int kO0 = G == 0 ? kEy : kEx;
@@ -640,7 +695,10 @@ __device__ __forceinline__ void z_group(const ZCol& z, float2 (&pre)[8], const f
 // p-pol (Ex, Ez, By) with sources.  The coefficients are evaluated once, in
 // the first phase; C and S stay in registers and the third coefficient that a
 // later phase needs goes to the thread's own LDS slots (cx[t + 512 q], written
-// and read by the same thread only, so no barrier is involved).
+// and read by the same thread only, so no barrier is involved).  The slots are
+// FP32: the two transition buffers leave 16 KB of LDS, and a coefficient
+// rounded to FP32 adds an error of the same size as the FP32 rounding of the
+// result it multiplies into (the arithmetic stays FP64).
 //   rho form:  rho_old, rho_new: Ex' = i kx R, Ez' = i kz R, R = X3 rho_old - X2 rho_new
 //                                (cx = X1)
 //              Jx: Ex' -= (S/eps0) Jx, By' = i X1 kz Jx
@@ -652,11 +710,11 @@ __device__ __forceinline__ void z_group(const ZCol& z, float2 (&pre)[8], const f
 //              Ex: Ex' += C Ex + L1 kx kx Ex, Ez' += L1 kz kx Ex, By' -= i S kz Ex
 //              Ez: Ez' += C Ez + L1 kz kz Ez, Ex' += L1 kx kz Ez, By' += i S kx Ez
 template <int SRC>
-__device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx, float2 (&pre)[8],
+__device__ __forceinline__ void z_ppol_sources(ZCol& z, float* cx, float2 (&pre)[8],
                                                const float2* next) {
   static_assert(SRC == kRho || SRC == kJForm, "source forms only");
   const double kx = z.kx, c2 = z.c2;
-  const int t = z.t;
+  const int t = z.x.tB;
   float2 acc[3][8];
   double cC[8], cS[8];
   if constexpr (SRC == kRho) {
@@ -670,7 +728,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx, float2
         const Coef cf = z.coef(kz);
         cC[q] = cf.C;
         cS[q] = cf.S;
-        cx[t + 512 * q] = cf.X1;
+        cx[t + 512 * q] = static_cast<float>(cf.X1);
         const double2 o = ld2(ro[q]), n = ld2(rn[q]);
         const double2 R = make_double2(cf.X3 * o.x - cf.X2 * n.x, cf.X3 * o.y - cf.X2 * n.y);
         acc[0][q] = st2(make_double2(-kx * R.y, kx * R.x));
@@ -721,7 +779,7 @@ __device__ __forceinline__ void z_ppol_sources(const ZCol& z, double* cx, float2
       const Coef cf = z.coef(kz);
       cC[q] = cf.C;
       cS[q] = cf.S;
-      cx[t + 512 * q] = z.eps0 * c2 * cf.X1;
+      cx[t + 512 * q] = static_cast<float>(z.eps0 * c2 * cf.X1);
       double2 a, b, c;
       const double2 zero = make_double2(0.0, 0.0);
       src_2d_p<kJForm>(kx, kz, cf, z.dt, ld2(jx[q]), ld2(jz[q]), zero, zero, a, b, c);
@@ -826,17 +884,17 @@ __global__ void __launch_bounds__(512)
 z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
                int nitems, float* __restrict__ ws, Physics ph) {
   extern __shared__ double2 lds2[];
-  double2* bufA = lds2;
-  double2* bufB = lds2 + kNZ;
-  double* cx = reinterpret_cast<double*>(lds2 + 2 * kNZ);  // one coefficient per mode
+  // two transition buffers, then one coefficient per mode (FP32, see z_ppol_sources)
+  float* cx = reinterpret_cast<float*>(lds2 + 2 * kZBuf);
   int it = blockIdx.x;
   if (it >= nitems) return;
   int patch = items[it].patch, kxcol = items[it].first;
   float2 pre[8];
-  z_load(make_zcol(patches + patch, kxcol, ws, ph, bufA, bufB).src(ZOrder<SRC>::kFirstS), pre,
+  z_load(make_zcol(patches + patch, kxcol, ws, ph, lds2, 0).src(ZOrder<SRC>::kFirstS), pre,
          threadIdx.x);
+  int tr = 0;  // transforms done so far: selects the transition buffer
   for (; it < nitems; it += gridDim.x) {
-    const ZCol z = make_zcol(patches + patch, kxcol, ws, ph, bufA, bufB);
+    ZCol z = make_zcol(patches + patch, kxcol, ws, ph, lds2, tr);
     // The p group's last phase prefetches the next column's first input; after
     // the last column it re-reads this column's (never used).
     const int nit = it + gridDim.x;
@@ -851,6 +909,7 @@ z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict_
       z_group<1, kVacuum>(z, pre, next);
     else
       z_ppol_sources<SRC>(z, cx, pre, next);
+    tr = z.tr;
     patch = npatch;
     kxcol = nkx;
   }
@@ -906,7 +965,7 @@ hipError_t configure_attributes() {
 }
 
 size_t x_lds_bytes() { return sizeof(double) * kRegion * kWaves; }
-size_t z_lds_bytes() { return sizeof(double2) * 2 * kNZ + sizeof(double) * kNZ; }
+size_t z_lds_bytes() { return sizeof(double2) * 2 * kZBuf + sizeof(float) * kNZ; }
 
 }  // namespace fast2d
 }  // namespace psatd

@@ -49,6 +49,8 @@ struct PatchDev {
   const double* kx;       // [mx]  k_x of packed column j (column 0: k_x = 0)
   const double* ky;       // [ny]
   const double* kz;       // [nz]
+  const double* kz_b;     // [nz] nz = 4096 only: kz_b[64 k2 + j + 512 q] = kz[8 j + k2 + 512 q],
+                          // the order in which the 4096-point z pass updates its modes
   const double2* post;    // [mx]  exp(-2 pi i j / nx), r2c post-twiddles
   FFTPlanDev fx;          // length mx
   FFTPlanDev fy;          // length ny (3D)
