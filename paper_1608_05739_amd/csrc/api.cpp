@@ -8,6 +8,8 @@
 #include <cstring>
 #include <exception>
 #include <map>
+#include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -861,12 +863,17 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
       return fail(PSATD_ERR_INVALID_ARG, "device index out of range");
     DeviceGuard g(device);
     if (!g.ok) return fail(PSATD_ERR_HIP, "hipSetDevice failed");
-    static bool attrs = false;
-    if (!attrs) {
-      hipError_t e = configure_kernel_attributes();
-      if (e == hipSuccess) e = fast2d::configure_attributes();
-      if (e != hipSuccess) return hip_fail(e, "kernel attributes");
-      attrs = true;
+    {
+      // the dynamic-LDS limit of every kernel, raised once per device
+      static std::mutex mu;
+      static std::set<int> configured;
+      std::lock_guard<std::mutex> lock(mu);
+      if (!configured.count(device)) {
+        hipError_t e = configure_kernel_attributes();
+        if (e == hipSuccess) e = fast2d::configure_attributes();
+        if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+        configured.insert(device);
+      }
     }
     psatd_plan_s* plan = new psatd_plan_s();
     plan->cfg = *cfg;
