@@ -236,6 +236,56 @@ def run_fp64(pk, w, mode, cells, steps, args, vacuum_batch):
     return fp64
 
 
+def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
+    """Guard-cell decomposition of the workload's grid: cell-steps/s of the
+    global grid (interior cells), beside the undecomposed plan at the same
+    order, with the relative difference of the two after the timed steps."""
+    import torch
+
+    steps = args.steps or 100
+    w = build_inputs(args.workload, steps)
+    p = w.patches[0]
+    mode = "rho" if w.sources else "vacuum"
+    dom = pk.Domain(len(p.shape), (p.nx, p.ny, p.nz), parts, (guard, guard, guard), p.d, p.dt,
+                    precision="fp32", source_mode=mode, order=order, centered_stencil=True,
+                    graph=True)
+    npatch, local = dom.local_shape
+    plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", order=order,
+                   centered_stencil=True, graph=True, autotune=True)
+    E, B, J, ro, rn = device_fields(w, plan, np.float32)
+    E2 = [t.clone() for t in E]
+    B2 = [t.clone() for t in B]
+
+    def run_dom(n):
+        for _ in range(n):
+            if w.sources:
+                dom.push(E2, B2, J, ro, rn, steps=1)
+            else:
+                dom.push(E2, B2, steps=1)
+
+    run_dom(min(args.warmup, 5))
+    torch.cuda.synchronize()
+    log(f"[bench] timing {steps} decomposed steps: {npatch} patches of {local} ...")
+    t0 = time.perf_counter()
+    run_dom(steps)
+    torch.cuda.synchronize()
+    sec_dom = time.perf_counter() - t0
+    sec_glob = time_steps(plan, E, B, J, ro, rn, steps, min(args.warmup, 5), not w.sources)
+    diff = float(np.sqrt(sum(float(torch.sum((a.double() - b.double()) ** 2)) for a, b in zip(E + B, E2 + B2))
+                         / sum(float(torch.sum(b.double() ** 2)) for b in E + B)))
+    out = {"metric": "PSATD guard-cell decomposition cell-steps/s (global interior cells), 1 GPU",
+           "value": w.cells * steps / sec_dom, "unit": "cell-steps/s", "n_gpus": 1, "steps": steps,
+           "ms_per_step": 1e3 * sec_dom / steps, "higher_is_better": True, "dtype": "f64",
+           "config": {"workload": w.name, "parts": list(parts), "guard": guard, "order": order,
+                      "stencil": "centered", "patches": npatch, "local_shape": list(local),
+                      "storage": "f32"},
+           "undecomposed": {"value": w.cells * steps / sec_glob, "ms_per_step": 1e3 * sec_glob / steps},
+           "rel_l2_vs_undecomposed": diff}
+    dom.close()
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +299,9 @@ def main():
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--decomposition", action="store_true",
+                    help="instead of the default line: time the guard-cell domain decomposition "
+                         "(2 x 2 boxes, 128 guard cells, centered order 16) on the same workload")
     ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: store HBM bytes per pass from two rocprofv3 --pmc counter "
                          "files (FETCH_SIZE, WRITE_SIZE) of this script, scaled by its "
@@ -278,6 +331,8 @@ def main():
         log(f"[bench] calibration copy: {args.copy_calibration_mib} MiB read + written")
         del src, dst
     index = args.workload
+    if args.decomposition:
+        return bench_decomposition(pk, args)
     default_steps = {0: 100, 1: 1000, 2: 200, 3: 500, 4: 100}[index]
     steps = args.steps if args.steps is not None else default_steps
     w = build_inputs(index, steps)
