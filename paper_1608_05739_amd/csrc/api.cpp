@@ -121,6 +121,8 @@ struct Pass {
   double bytes = 0.0;
   int mpt = 0;
   double tuned_ms = -1.0;  // mean launch time at the chosen grid (autotune), else -1
+  std::vector<int> comps;  // line passes: the components they transform
+  int lines = 0;           // line passes: lines per workgroup (the tile)
 };
 
 const char* line_pass_name(int kind) {
@@ -154,6 +156,7 @@ struct psatd_plan_s {
   bool ws_owned = false;
   size_t ws_bytes = 0;
   std::vector<Pass> passes;
+  std::vector<void*> extra_items;  // work lists of passes the autotuner re-tiled
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -171,6 +174,8 @@ void free_plan_memory(psatd_plan_s* p) {
   if (p->d_patches) (void)hipFree(p->d_patches);
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_items) (void)hipFree(p->d_items);
+  for (void* x : p->extra_items) (void)hipFree(x);
+  p->extra_items.clear();
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
   p->graph_exec = nullptr;
   p->graph = nullptr;
@@ -277,7 +282,9 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
     int nlines, L;
     line_geometry(kind, P, &nlines, &L);
     int R;
-    if (transposing) {
+    if (lines_override > 0) {
+      R = lines_override;
+    } else if (transposing) {
       R = want;
     } else {
       R = std::max(1, 4096 / L);
@@ -288,6 +295,7 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
     R = std::max(1, std::min(R, max_pts / L));
     block = std::max(block, threads_for(R * L, L));
     lds = std::max(lds, static_cast<size_t>(R) * L * sizeof(double2));
+    ps.lines = std::max(ps.lines, R);
     for (int c : comps)
       for (int l = 0; l < nlines; l += R)
         items.push_back(WorkItem{static_cast<int>(pi), l, std::min(R, nlines - l), c});
@@ -297,6 +305,7 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
   ps.nitems = static_cast<int>(items.size() - first);
   ps.shape = LaunchShape{ps.nitems, std::min(block, kLineBlockMax), lds};
   ps.bytes = bytes;
+  ps.comps = comps;
   ps.d_items = reinterpret_cast<WorkItem*>(first);  // offset, fixed up after upload
   return ps;
 }
@@ -604,33 +613,77 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
   FieldPtrs f{};
   for (int c = 0; c < plan->nin; ++c) f.f[c] = static_cast<char*>(fields) + c * comp_bytes;
   constexpr int kReps = 3;
+  // Mean ms of one launch of `ps` (warm-up first), or a negative value on error.
+  auto time_pass = [&](const Pass& ps) -> double {
+    st = enqueue_pass(plan, ps, f, s);
+    if (st != PSATD_OK) return -1.0;
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < kReps && st == PSATD_OK && e == hipSuccess; ++r) st = enqueue_pass(plan, ps, f, s);
+    if (st != PSATD_OK) return -1.0;
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    return e == hipSuccess ? ms / kReps : -1.0;
+  };
   for (Pass& ps : plan->passes) {
-    std::vector<int> cands = {ps.nitems};
-    for (int k : {1, 2, 4})
-      if (k * plan->num_cus < ps.nitems) cands.push_back(k * plan->num_cus);
-    int best = ps.shape.grid;
-    double best_ms = 1e300;
-    for (int g : cands) {
-      ps.shape.grid = g;
-      st = enqueue_pass(plan, ps, f, s);  // warm-up
-      if (st != PSATD_OK) break;
-      e = hipEventRecord(e0, s);
-      for (int r = 0; r < kReps && st == PSATD_OK && e == hipSuccess; ++r)
-        st = enqueue_pass(plan, ps, f, s);
-      if (st != PSATD_OK) break;
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
-      const double per = ms / kReps;
-      if (per < best_ms) {
-        best_ms = per;
-        best = g;
+    // Candidate tiles: line passes are rebuilt with other lines-per-workgroup
+    // counts (each work list checked on the host, then uploaded); every tile
+    // is timed at each candidate grid.
+    struct Cand {
+      Pass pass;
+      WorkItem* d = nullptr;  // owned device work list (nullptr: the plan's)
+    };
+    std::vector<Cand> cands;
+    cands.push_back(Cand{ps, nullptr});
+    if (ps.type == kLine) {
+      for (int R : {1, 2, 4, 8, 16, 32}) {
+        std::vector<WorkItem> its;
+        Pass c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
+        bool seen = false;
+        for (const Cand& x : cands) seen = seen || x.pass.lines == c.lines;
+        if (seen) continue;
+        c.d_items = nullptr;
+        if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
+        WorkItem* d = nullptr;
+        e = hipMalloc(&d, sizeof(WorkItem) * its.size());
+        if (e == hipSuccess)
+          e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+          if (d) (void)hipFree(d);
+          break;
+        }
+        c.d_items = d;
+        cands.push_back(Cand{c, d});
       }
     }
-    ps.shape.grid = best;
+    int best_c = 0, best_g = ps.shape.grid;
+    double best_ms = 1e300;
+    for (size_t ci = 0; ci < cands.size() && st == PSATD_OK && e == hipSuccess; ++ci) {
+      Pass& c = cands[ci].pass;
+      std::vector<int> grids = {c.nitems};
+      for (int k : {1, 2, 4})
+        if (k * plan->num_cus < c.nitems) grids.push_back(k * plan->num_cus);
+      for (int g : grids) {
+        c.shape.grid = g;
+        const double ms = time_pass(c);
+        if (ms < 0.0) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_c = static_cast<int>(ci);
+          best_g = g;
+        }
+      }
+    }
+    for (size_t ci = 1; ci < cands.size(); ++ci)
+      if (static_cast<int>(ci) != best_c || st != PSATD_OK || e != hipSuccess)
+        (void)hipFree(cands[ci].d);
     if (st != PSATD_OK || e != hipSuccess) break;
+    if (best_c != 0) {
+      ps = cands[best_c].pass;
+      plan->extra_items.push_back(cands[best_c].d);
+    }
+    ps.shape.grid = best_g;
     ps.tuned_ms = best_ms;
   }
   cleanup();
@@ -837,9 +890,10 @@ psatd_status build_plan(psatd_plan_s* plan) {
                 plan->ws_bytes);
   plan->info += buf;
   for (const Pass& ps : plan->passes) {
-    std::snprintf(buf, sizeof(buf), "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d bytes=%.0f%s\n",
+    std::snprintf(buf, sizeof(buf),
+                  "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d lines=%d bytes=%.0f%s\n",
                   ps.name, ps.nitems, ps.shape.grid, ps.shape.block, ps.shape.lds_bytes, ps.mpt,
-                  ps.bytes, ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
+                  ps.lines, ps.bytes, ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
     plan->info += buf;
   }
   return PSATD_OK;
