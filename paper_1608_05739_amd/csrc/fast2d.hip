@@ -209,6 +209,14 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
                                                  static_cast<float>(c[b][q].y));
     __syncthreads();
 
+    // Output-phase constants, loaded before the next row: loads complete in
+    // order, so waiting for a load issued after the prefetch would wait for
+    // the whole prefetch.  post[t + 512 i] = post[t] post[512]^i and
+    // W4096^(z1 k2) = (W4096^z1)^k2 follow by multiplication.
+    const double2 wk0 = P->post[threadIdx.x];
+    const double2 wstep = P->post[512];
+    const double2 wz1 = tw4096[z1];
+    __builtin_amdgcn_sched_barrier(0);
     // next tile's row (the same workgroup's next item), in flight during the output phase
     const int nit = it + gridDim.x;
     if (nit < nitems) {
@@ -218,14 +226,16 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 
     // output phase: kx = t + 512 i
     double2 tz[8];
+    tz[0] = make_double2(1.0, 0.0);
+    tz[1] = wz1;
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) tz[k2] = tw4096[(z1 * k2) & (kNZ - 1)];
+    for (int k2 = 2; k2 < 8; ++k2) tz[k2] = cmul(tz[k2 - 1], wz1);
+    double2 wk = wk0;
     float2* out = reinterpret_cast<float2*>(ws) + P->off_spec + (long long)wi.comp * P->comp_stride;
 #pragma unroll 1
     for (int i = 0; i < 4; ++i) {
       const int kx = threadIdx.x + 512 * i;
       const int km = (kMX - kx) & (kMX - 1);
-      const double2 wk = P->post[kx];
       double2 X[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -247,6 +257,7 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
         dst[k2 / 2] = make_float4(static_cast<float>(u.x), static_cast<float>(u.y),
                                   static_cast<float>(v.x), static_cast<float>(v.y));
       }
+      wk = cmul(wk, wstep);
     }
     __syncthreads();
   }
