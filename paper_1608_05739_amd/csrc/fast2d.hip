@@ -25,11 +25,10 @@ namespace fast2d {
 constexpr int kMX = 2048;    // complex points per x line (nx = 4096)
 constexpr int kNZ = 4096;    // z line length
 constexpr int kN1 = 512;     // z1 range
-constexpr int kN2 = 8;       // z2 range (rows per tile)
 constexpr int kWaves = 8;    // one wave per row of a tile
 constexpr int kRegion = kMX + kMX / 16;  // doubles per wave region (padded)
 
-__device__ __forceinline__ int padx(int i) { return i + (i >> 4); }
+// Wave regions are padded: logical index i sits at padx(i) = i + (i >> 4).
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
 // XCD b mod 8, and about 256 run at once, one per CU).  Within each run of 256
@@ -49,15 +48,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int N>
-__device__ __forceinline__ void powers(double2 w, double2* wp) {
-  // wp[q] = w^q, q = 0..N-1
-  wp[0] = make_double2(1.0, 0.0);
-  wp[1] = w;
-#pragma unroll
-  for (int q = 2; q < N; ++q) wp[q] = cmul(wp[q - 1], w);
 }
 
 // Exchange 32 complex values through a wave region: value (b, q) is written at
@@ -435,11 +425,6 @@ __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx
   DFT<8, -1>::run(v);
 }
 
-// conjugate twiddles applied after the butterflies (adjoint of twiddle8<-1>)
-__device__ __forceinline__ void twiddle8_adj(double2 (&v)[8], double2 w) {
-  twiddle8<1>(v, w);
-}
-
 // Inverse (unnormalized, the adjoint of fwd512): v holds elements jB + 64 q of
 // group k2B (mapping B) on entry and elements jA + 64 q of group k2A
 // (mapping A) on exit.
@@ -449,7 +434,7 @@ __device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx
   double2* b2 = buf + x.baseB2;
   // adjoint of stage 3
   DFT<8, 1>::run(v);
-  twiddle8_adj(v, tw4096[8 * x.jB]);
+  twiddle8<1>(v, tw4096[8 * x.jB]);  // conjugate twiddles after the butterflies
 #pragma unroll
   for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
   wave_lds_sync();
@@ -457,7 +442,7 @@ __device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx
   for (int q = 0; q < 8; ++q) v[q] = b2[8 * q];
   // adjoint of stage 2
   DFT<8, 1>::run(v);
-  twiddle8_adj(v, tw4096[64 * (x.jB & 7)]);
+  twiddle8<1>(v, tw4096[64 * (x.jB & 7)]);
 #pragma unroll
   for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
   __syncthreads();

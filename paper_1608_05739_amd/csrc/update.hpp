@@ -187,105 +187,22 @@ __device__ __forceinline__ void update_mode(const double kx, const double ky, co
 //                  = eps0 c^2 X1 k (k.E) - dt X2 k (k.J)                 (J form)
 // These are the general update with k_y = 0 written out, so that no term is
 // multiplied by an explicit zero.
+
+// FP32 storage <-> FP64 arithmetic.
 __device__ __forceinline__ double2 ld2(const float2& v) { return make_double2(v.x, v.y); }
 __device__ __forceinline__ float2 st2(double2 v) {
   return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
 }
-__device__ __forceinline__ double2 ld2(const double2& v) { return v; }
-template <typename V>
-__device__ __forceinline__ V st2t(double2 v);
-template <>
-__device__ __forceinline__ float2 st2t<float2>(double2 v) { return st2(v); }
-template <>
-__device__ __forceinline__ double2 st2t<double2>(double2 v) { return v; }
 
-// in/out: Ey, Bx, Bz (updated in place), Jy (read, sources only)
-template <int SRC, typename V>
-__device__ __forceinline__ void update_2d_s(double kx, double kz, const Coef& q, double c,
-                                            double eps0, V& Ey, V& Bx, V& Bz, const V Jy) {
-  const double2 ey = ld2(Ey), bx = ld2(Bx), bz = ld2(Bz);
-  const double cS = c * c * q.S;
-  const double2 kb = make_double2(kz * bx.x - kx * bz.x, kz * bx.y - kx * bz.y);
-  double2 ey2 = make_double2(q.C * ey.x - cS * kb.y, q.C * ey.y + cS * kb.x);
-  double2 bx2 = make_double2(q.C * bx.x - q.S * kz * ey.y, q.C * bx.y + q.S * kz * ey.x);
-  double2 bz2 = make_double2(q.C * bz.x + q.S * kx * ey.y, q.C * bz.y - q.S * kx * ey.x);
-  if constexpr (SRC != kVacuum) {
-    const double2 jy = ld2(Jy);
-    const double sj = q.S / eps0;
-    ey2.x -= sj * jy.x;
-    ey2.y -= sj * jy.y;
-    bx2.x += q.X1 * kz * jy.y;
-    bx2.y -= q.X1 * kz * jy.x;
-    bz2.x -= q.X1 * kx * jy.y;
-    bz2.y += q.X1 * kx * jy.x;
-  }
-  Ey = st2t<V>(ey2);
-  Bx = st2t<V>(bx2);
-  Bz = st2t<V>(bz2);
-}
-
-// in/out: Ex, Ez, By (updated in place); Jx, Jz, rho_old, rho_new (read)
-template <int SRC, typename V>
-__device__ __forceinline__ void update_2d_p(double kx, double kz, const Coef& q, double c,
-                                            double eps0, double dt, V& Ex, V& Ez, V& By,
-                                            const V Jx, const V Jz, const V ro, const V rn) {
-  const double2 ex = ld2(Ex), ez = ld2(Ez), by = ld2(By);
-  const double cS = c * c * q.S;
-  // E' = C E + i c^2 S (k x B): (k x B)_x = -kz By, (k x B)_z = kx By
-  double2 ex2 = make_double2(q.C * ex.x + cS * kz * by.y, q.C * ex.y - cS * kz * by.x);
-  double2 ez2 = make_double2(q.C * ez.x - cS * kx * by.y, q.C * ez.y + cS * kx * by.x);
-  // B' = C B - i S (k x E)_y, (k x E)_y = kz Ex - kx Ez
-  const double2 ke = make_double2(kz * ex.x - kx * ez.x, kz * ex.y - kx * ez.y);
-  double2 by2 = make_double2(q.C * by.x + q.S * ke.y, q.C * by.y - q.S * ke.x);
-  if constexpr (SRC == kJForm) {
-    const double a = eps0 * c * c * q.X1;
-    const double2 kdE = make_double2(kx * ex.x + kz * ez.x, kx * ex.y + kz * ez.y);
-    ex2.x += a * kx * kdE.x;
-    ex2.y += a * kx * kdE.y;
-    ez2.x += a * kz * kdE.x;
-    ez2.y += a * kz * kdE.y;
-  }
-  if constexpr (SRC != kVacuum) {
-    const double2 jx = ld2(Jx), jz = ld2(Jz);
-    const double sj = q.S / eps0;
-    ex2.x -= sj * jx.x;
-    ex2.y -= sj * jx.y;
-    ez2.x -= sj * jz.x;
-    ez2.y -= sj * jz.y;
-    // + i X1 (kz Jx - kx Jz)
-    const double2 kj = make_double2(kz * jx.x - kx * jz.x, kz * jx.y - kx * jz.y);
-    by2.x -= q.X1 * kj.y;
-    by2.y += q.X1 * kj.x;
-    if constexpr (SRC == kJForm) {
-      const double b = dt * q.X2;
-      const double2 kdJ = make_double2(kx * jx.x + kz * jz.x, kx * jx.y + kz * jz.y);
-      ex2.x -= b * kx * kdJ.x;
-      ex2.y -= b * kx * kdJ.y;
-      ez2.x -= b * kz * kdJ.x;
-      ez2.y -= b * kz * kdJ.y;
-    } else {
-      const double2 r0 = ld2(ro), r1 = ld2(rn);
-      const double2 lam = make_double2(q.X3 * r0.x - q.X2 * r1.x, q.X3 * r0.y - q.X2 * r1.y);
-      // + i k lam
-      ex2.x -= kx * lam.y;
-      ex2.y += kx * lam.x;
-      ez2.x -= kz * lam.y;
-      ez2.y += kz * lam.x;
-    }
-  }
-  Ex = st2t<V>(ex2);
-  Ez = st2t<V>(ez2);
-  By = st2t<V>(by2);
-}
-
-// ------------------------------------------------------------------ 2D, phased
-// The same 2D update split into a source part, evaluated once the sources are
-// transformed, and a field part.  The source part returns the contributions
+// ------------------------------------------------------------------ 2D, sources
+// The source part of the 2D update, evaluated once the sources are
+// transformed (the field part is accumulated term by term by the z pass).
+// It returns the contributions
 //   s-pol: sEy = -(S/eps0) Jy,  sBx = -i X1 kz Jy,  sBz = i X1 kx Jy
 //   p-pol: sEx = -(S/eps0) Jx + Lx,  sEz = -(S/eps0) Jz + Lz,  sBy = i X1 (kz Jx - kx Jz)
 //          L = i k (X3 rho_old - X2 rho_new)      (rho form)
 //          L = -dt X2 k (k.J)                      (J form)
-// and the field part adds them to C E + i c^2 S (k x B) [+ eps0 c^2 X1 k (k.E),
+// to which the field part adds C E + i c^2 S (k x B) [+ eps0 c^2 X1 k (k.E),
 // J form] and C B - i S (k x E).
 __device__ __forceinline__ void src_2d_s(double kx, double kz, const Coef& q, double2 jy,
                                          double2& sEy, double2& sBx, double2& sBz) {
@@ -316,40 +233,6 @@ __device__ __forceinline__ void src_2d_p(double kx, double kz, const Coef& q, do
     sEz.x -= kz * lam.y;
     sEz.y += kz * lam.x;
   }
-}
-
-// s-pol field part, in place; (sEy, sBx, sBz) = 0 in vacuum.
-__device__ __forceinline__ void fld_2d_s(double kx, double kz, double C, double S, double c,
-                                         double2& ey, double2& bx, double2& bz, double2 sEy,
-                                         double2 sBx, double2 sBz) {
-  const double cS = c * c * S;
-  const double2 kb = make_double2(kz * bx.x - kx * bz.x, kz * bx.y - kx * bz.y);
-  const double2 e0 = ey;
-  ey = make_double2(C * e0.x - cS * kb.y + sEy.x, C * e0.y + cS * kb.x + sEy.y);
-  bx = make_double2(C * bx.x - S * kz * e0.y + sBx.x, C * bx.y + S * kz * e0.x + sBx.y);
-  bz = make_double2(C * bz.x + S * kx * e0.y + sBz.x, C * bz.y - S * kx * e0.x + sBz.y);
-}
-
-// p-pol field part, in place.  L1 = eps0 c^2 X1 (J form only, else unused).
-template <int SRC>
-__device__ __forceinline__ void fld_2d_p(double kx, double kz, double C, double S, double L1,
-                                         double c, double2& ex, double2& ez, double2& by,
-                                         double2 sEx, double2 sEz, double2 sBy) {
-  const double cS = c * c * S;
-  const double2 ke = make_double2(kz * ex.x - kx * ez.x, kz * ex.y - kx * ez.y);
-  const double2 b0 = by;
-  double2 ex2 = make_double2(C * ex.x + cS * kz * b0.y + sEx.x, C * ex.y - cS * kz * b0.x + sEx.y);
-  double2 ez2 = make_double2(C * ez.x - cS * kx * b0.y + sEz.x, C * ez.y + cS * kx * b0.x + sEz.y);
-  if constexpr (SRC == kJForm) {
-    const double2 kdE = make_double2(kx * ex.x + kz * ez.x, kx * ex.y + kz * ez.y);
-    ex2.x += L1 * kx * kdE.x;
-    ex2.y += L1 * kx * kdE.y;
-    ez2.x += L1 * kz * kdE.x;
-    ez2.y += L1 * kz * kdE.y;
-  }
-  by = make_double2(C * b0.x + S * ke.y + sBy.x, C * b0.y - S * ke.x + sBy.y);
-  ex = ex2;
-  ez = ez2;
 }
 
 }  // namespace psatd
