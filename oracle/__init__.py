@@ -13,6 +13,9 @@ Contents
   dispersion  refractive-index formulas of Table 1, the Snell-Descartes
               refraction model of Sec. IV (eq. 1) and a CPU Yee FDTD stepper,
               used only as the contrast the paper draws against PSATD.
+  contrast    the contrast solvers as full field steps (Sec. III.A, Table 1):
+              Yee and order-p FDTD on the staggered grid, CKC, and PSTD.
+  decomposition  the guard-cell domain decomposition (Sec. II.A).
 
 Pins (see tests/test_oracle_*.py): brute-force O(N^2) DFT sums, the matrix
 exponential of the per-mode Maxwell system, exact lattice plane-wave phase,
