@@ -73,6 +73,16 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
  * Its symbol vanishes smoothly at the Nyquist wavenumber, so every operator of
  * the step stays local in real space (what guard-cell decompositions need). */
 #define PSATD_FLAG_CENTERED_STENCIL 0x10u
+/* The PSTD contrast solver (Table 1, PSTD row) instead of PSATD: the same
+ * transforms and k tables, but a leapfrog in time, E at integer and B at
+ * half-integer times.  One push takes E^n, B^{n-1/2}, J^{n+1/2} to
+ *   B^{n+1/2} = B^{n-1/2} - dt curl E^n,
+ *   E^{n+1}   = E^n + dt (c^2 curl B^{n+1/2} - J^{n+1/2} / eps0)
+ * with curl -> i k x.  source_mode must be PSATD_VACUUM or PSATD_SOURCES_J
+ * (PSTD uses no rho); the generic kernels run it.  Planning fails with
+ * PSATD_ERR_INVALID_ARG when c dt |k|max / 2 > 1 for a patch (its Courant
+ * condition; |k|max over the patch's k table). */
+#define PSATD_FLAG_PSTD 0x20u
 
 typedef struct {
   int32_t ndim;  /* 2: (x, z) plane, n[1] must be 1;  3: (x, y, z)                   */
@@ -203,6 +213,52 @@ psatd_status psatd_domain_push(psatd_domain_t domain, const psatd_fields* global
                                int32_t nsteps, void* hip_stream);
 
 psatd_status psatd_domain_destroy(psatd_domain_t domain);
+
+/* ---------------------------------------------------------------------------
+ * FDTD contrast solvers (Sec. III.A; Table 1, Yee, CKC and FDTD p-order rows):
+ * the finite-difference schemes the paper measures PSATD against.  No kernel
+ * is shared with the PSATD path.
+ *
+ * Leapfrog: E at integer times, B at half-integer times.  One step takes
+ * E^n, B^{n-1/2}, J^{n+1/2} to
+ *   B^{n+1/2} = B^{n-1/2} - dt curl+ E^n
+ *   E^{n+1}   = E^n + dt (c^2 curl- B^{n+1/2} - J^{n+1/2} / eps0)
+ * on the periodic Yee grid.  Each component array is dense [nz][ny][nx]
+ * (x fastest; [nz][nx] in 2D) at the patch's offset, element (i, j, k)
+ * holding the component at its staggered position:
+ *   Ex (i+1/2, j, k)  Ey (i, j+1/2, k)  Ez (i, j, k+1/2)   (J likewise)
+ *   Bx (i, j+1/2, k+1/2)  By (i+1/2, j, k+1/2)  Bz (i+1/2, j+1/2, k)
+ * curl+ uses forward and curl- backward differences with the staggered
+ * order-p weights C_l of Sec. III.B (p = 2: nearest neighbours, the Yee
+ * scheme).  PSATD_FDTD_CKC (2D, dx = dz, order 2) averages, in curl+ only,
+ * each x-difference over z and each z-difference over x with weights
+ * (3/4, 1/8, 1/8) (beta = 1/4).
+ * ------------------------------------------------------------------------- */
+typedef struct psatd_fdtd_s* psatd_fdtd_t;
+
+enum { PSATD_FDTD_YEE = 0, PSATD_FDTD_CKC = 1 };
+
+/* Plan one periodic patch.  config: precision (field element type),
+ * source_mode PSATD_VACUUM or PSATD_SOURCES_J, order 0 or 2 (second order) or
+ * an even p <= 32 (Yee scheme only), c, eps0; path and flags must be 0.
+ * patch: ndim 2 (n[1] = 1) or 3 (CKC: 2 only), max(2, p) <= n[a] <= 2^24, at
+ * most 2^31 cells, d > 0, offset >= 0.  dt must satisfy the scheme's Courant
+ * condition: c dt sqrt(sum_a (sum_l |C_l| / d_a)^2) <= 1 (Yee, order p), or
+ * c dt <= dx (CKC); otherwise PSATD_ERR_INVALID_ARG.  Allocates no device
+ * memory; *out is set only on success. */
+psatd_status psatd_fdtd_plan(const psatd_config* config, int32_t scheme,
+                             const psatd_patch_desc* patch, int32_t device, psatd_fdtd_t* out);
+
+/* Advance E and B in place by nsteps steps on hip_stream (J read when
+ * source_mode is PSATD_SOURCES_J; nsteps > 1 only in vacuum).  Two kernel
+ * launches per step (the B half, then the E half), asynchronous, no
+ * allocation and no synchronization.  Argument errors are returned before
+ * anything is enqueued. */
+psatd_status psatd_fdtd_push(psatd_fdtd_t fdtd, const psatd_fields* fields, int32_t nsteps,
+                             void* hip_stream);
+
+/* Free the plan (it owns no device memory).  NULL is accepted. */
+psatd_status psatd_fdtd_destroy(psatd_fdtd_t fdtd);
 
 #ifdef __cplusplus
 }

@@ -8,6 +8,7 @@ fallback: if the library is not built, loading it raises.
 from ._binding import (  # noqa: F401
     Domain,
     EXPORTED_SYMBOLS,
+    Fdtd,
     LIBRARY_PATH,
     Patch,
     Plan,

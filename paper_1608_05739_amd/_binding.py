@@ -29,12 +29,15 @@ FLAG_GRAPH = 0x2
 FLAG_NO_WORKSPACE = 0x4
 FLAG_GENERIC_KERNELS = 0x8
 FLAG_CENTERED_STENCIL = 0x10
+FLAG_PSTD = 0x20
+FDTD_SCHEME = {"yee": 0, "ckc": 1}
 
 EXPORTED_SYMBOLS = (
     "psatd_plan", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
     "psatd_push_profiled", "psatd_pass_count", "psatd_pass_name", "psatd_pass_bytes",
     "psatd_plan_info", "psatd_destroy", "psatd_status_string", "psatd_last_error",
     "psatd_domain_create", "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
+    "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy",
 )
 
 
@@ -108,10 +111,15 @@ def load_library(path: Optional[str] = None):
                                              ctypes.c_int64 * 3]
     lib.psatd_domain_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
     lib.psatd_domain_destroy.argtypes = [vp]
+    lib.psatd_fdtd_plan.argtypes = [ctypes.POINTER(Config), i32, ctypes.POINTER(PatchDesc), i32,
+                                    ctypes.POINTER(vp)]
+    lib.psatd_fdtd_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
+    lib.psatd_fdtd_destroy.argtypes = [vp]
     for name in ("psatd_plan", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
                  "psatd_push_profiled", "psatd_pass_count", "psatd_pass_bytes",
                  "psatd_plan_info", "psatd_destroy", "psatd_domain_create",
-                 "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy"):
+                 "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
+                 "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -154,7 +162,7 @@ def as_patch(p) -> Patch:
 
 def make_config(precision="fp32", source_mode="vacuum", path="fused", order=0, c=1.0, eps0=1.0,
                 *, autotune=False, graph=False, allocate_workspace=True, generic_kernels=False,
-                centered_stencil=False) -> Config:
+                centered_stencil=False, pstd=False) -> Config:
     cfg = Config()
     cfg.precision = PRECISION[precision]
     cfg.source_mode = SOURCE_MODE[source_mode]
@@ -165,7 +173,8 @@ def make_config(precision="fp32", source_mode="vacuum", path="fused", order=0, c
     cfg.flags = ((FLAG_AUTOTUNE if autotune else 0) | (FLAG_GRAPH if graph else 0)
                  | (0 if allocate_workspace else FLAG_NO_WORKSPACE)
                  | (FLAG_GENERIC_KERNELS if generic_kernels else 0)
-                 | (FLAG_CENTERED_STENCIL if centered_stencil else 0))
+                 | (FLAG_CENTERED_STENCIL if centered_stencil else 0)
+                 | (FLAG_PSTD if pstd else 0))
     return cfg
 
 
@@ -202,12 +211,14 @@ class Plan:
 
     Component buffers are flat tensors holding every patch at its offset
     (by default the patches are packed in order, see :attr:`offsets`).
+    ``pstd=True`` runs the PSTD contrast solver instead (leapfrog: B holds B
+    at half-integer times; source_mode "vacuum" or "j").
     """
 
     def __init__(self, patches: Sequence, *, precision="fp32", source_mode="vacuum",
                  path="fused", order=0, c=1.0, eps0=1.0, autotune=False, graph=False,
                  device=0, allocate_workspace=True, generic_kernels=False,
-                 centered_stencil=False):
+                 centered_stencil=False, pstd=False):
         self._lib = load_library()
         self._plan = None
         ps = [as_patch(p) for p in patches]
@@ -234,7 +245,8 @@ class Plan:
             descs[i].offset = self.offsets[i]
         cfg = make_config(precision, source_mode, path, order, c, eps0, autotune=autotune,
                           graph=graph, allocate_workspace=allocate_workspace,
-                          generic_kernels=generic_kernels, centered_stencil=centered_stencil)
+                          generic_kernels=generic_kernels, centered_stencil=centered_stencil,
+                          pstd=pstd)
         handle = ctypes.c_void_p()
         _check(self._lib, self._lib.psatd_plan(ctypes.byref(cfg), descs, len(ps), int(device),
                                                 ctypes.byref(handle)))
@@ -374,6 +386,55 @@ class Domain:
         if self._dom is not None:
             self._lib.psatd_domain_destroy(self._dom)
             self._dom = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fdtd:
+    """FDTD contrast solver on one periodic patch (Sec. III.A, Table 1).
+
+    ``scheme`` is "yee" (order 2, or order p) or "ckc" (2D, dx = dz).  Fields
+    live on the staggered Yee grid, B at half-integer times; :meth:`push`
+    advances flat tensors of nx*ny*nz elements (at ``offset``) in place.
+    """
+
+    def __init__(self, scheme, patch, *, precision="fp32", source_mode="vacuum", order=0, c=1.0,
+                 eps0=1.0, offset=0, device=0):
+        self._lib = load_library()
+        self._h = None
+        p = as_patch(patch)
+        desc = PatchDesc()
+        desc.ndim = p.ndim
+        desc.n = (ctypes.c_int64 * 3)(*[int(v) for v in p.n])
+        desc.d = (ctypes.c_double * 3)(*[float(v) for v in p.d])
+        desc.dt = float(p.dt)
+        desc.offset = int(offset if p.offset is None else p.offset)
+        cfg = make_config(precision, source_mode, "fused", order, c, eps0)
+        handle = ctypes.c_void_p()
+        _check(self._lib, self._lib.psatd_fdtd_plan(ctypes.byref(cfg), FDTD_SCHEME[scheme],
+                                                     ctypes.byref(desc), int(device),
+                                                     ctypes.byref(handle)))
+        self._h = handle
+        self.precision = precision
+        self.elements = int(desc.offset) + p.cells
+
+    def push(self, E, B, J=None, steps=1, stream=None):
+        import torch
+
+        want = torch.float32 if self.precision == "fp32" else torch.float64
+        f = _field_struct(E, B, J, None, None, want, self.elements)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self._lib, self._lib.psatd_fdtd_push(self._h, ctypes.byref(f), int(steps),
+                                                     ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if self._h is not None:
+            self._lib.psatd_fdtd_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

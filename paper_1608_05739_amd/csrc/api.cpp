@@ -146,6 +146,7 @@ struct psatd_plan_s {
   int num_cus = 256;  // compute units of the device (persistent grids)
   int ndim = 2;
   int nin = 6;      // input components
+  int src_form = 0; // SourceForm run by the generic kernels (PSATD forms or PSTD)
   size_t elem = 4;  // sizeof storage scalar
   std::vector<psatd_patch_desc> desc;
   std::vector<PatchDev> host_patches;
@@ -191,6 +192,25 @@ psatd_status hip_fail(hipError_t e, const char* what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Largest |k| of one axis table: the exact lattice k with Nyquist -> 0, or the
+// order-p wavevector of the staggered or centered stencil at those k.
+double axis_kmax(int n, double d, const std::vector<double>& w, bool centered) {
+  double best = 0.0;
+  for (int j = 0; j <= n / 2; ++j) {
+    if (n % 2 == 0 && j == n / 2) continue;  // Nyquist -> 0
+    const double k = 2.0 * M_PI * j / (n * d);
+    double kp = k;
+    if (!w.empty()) {
+      kp = 0.0;
+      for (size_t l = 1; l <= w.size(); ++l)
+        kp += w[l - 1] * (2.0 / d) *
+              (centered ? std::sin(l * k * d) : std::sin((2.0 * l - 1.0) * k * d / 2.0));
+    }
+    best = std::max(best, std::fabs(kp));
+  }
+  return best;
+}
+
 psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t np) {
   if (!cfg) return fail(PSATD_ERR_INVALID_ARG, "cfg is NULL");
   if (!patches) return fail(PSATD_ERR_INVALID_ARG, "patches is NULL");
@@ -207,8 +227,10 @@ psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, 
   if (!(cfg->eps0 > 0.0) || !std::isfinite(cfg->eps0))
     return fail(PSATD_ERR_INVALID_ARG, "eps0 must be > 0");
   if (cfg->flags & ~(PSATD_FLAG_AUTOTUNE | PSATD_FLAG_GRAPH | PSATD_FLAG_NO_WORKSPACE |
-                     PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_CENTERED_STENCIL))
+                     PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_CENTERED_STENCIL | PSATD_FLAG_PSTD))
     return fail(PSATD_ERR_INVALID_ARG, "unknown flag bits");
+  if ((cfg->flags & PSATD_FLAG_PSTD) && cfg->source_mode == PSATD_SOURCES_RHO)
+    return fail(PSATD_ERR_INVALID_ARG, "PSTD takes J only: source_mode VACUUM or SOURCES_J");
   const int ndim = patches[0].ndim;
   std::vector<std::pair<int64_t, int64_t>> ranges;
   for (int i = 0; i < np; ++i) {
@@ -239,10 +261,31 @@ psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, 
   for (size_t i = 1; i < ranges.size(); ++i)
     if (ranges[i].first < ranges[i - 1].second)
       return fail(PSATD_ERR_INVALID_ARG, "patches overlap in the component buffers");
+  if (cfg->flags & PSATD_FLAG_PSTD) {
+    // the leapfrog is stable while c dt |k|max / 2 <= 1 (Table 1, PSTD row)
+    const bool centered = (cfg->flags & PSATD_FLAG_CENTERED_STENCIL) != 0;
+    std::vector<double> fw;
+    if (cfg->order > 0) fw = centered ? fornberg_centered(cfg->order) : fornberg_staggered(cfg->order);
+    for (int i = 0; i < np; ++i) {
+      const psatd_patch_desc& d = patches[i];
+      double k2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (d.ndim == 2 && a == 1) continue;
+        const double k = axis_kmax(static_cast<int>(d.n[a]), d.d[a], fw, centered);
+        k2 += k * k;
+      }
+      const double r = 0.5 * cfg->c * d.dt * std::sqrt(k2);
+      if (r > 1.0 + 1e-12)
+        return fail(PSATD_ERR_INVALID_ARG,
+                    "patch " + std::to_string(i) + ": PSTD needs c dt |k|max / 2 <= 1, got " +
+                        std::to_string(r) + " (Courant condition)");
+    }
+  }
   return PSATD_OK;
 }
 
 int inputs_for(int src) { return src == PSATD_VACUUM ? 6 : (src == PSATD_SOURCES_J ? 9 : 11); }
+
 
 // Lines of a line pass for one patch and its FFT length.
 void line_geometry(int kind, const PatchDev& P, int* nlines, int* L) {
@@ -444,7 +487,7 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
 // FP32 storage, fused path.
 bool fast2d_eligible(const psatd_plan_s* plan) {
   const psatd_config& c = plan->cfg;
-  if (c.flags & PSATD_FLAG_GENERIC_KERNELS) return false;
+  if (c.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_PSTD)) return false;
   if (plan->ndim != 2 || c.precision != PSATD_FP32 || c.path != PSATD_PATH_FUSED) return false;
   for (const PatchDev& P : plan->host_patches)
     if (P.nx != fast2d::kNX || P.nz != fast2d::kNZfast) return false;
@@ -497,11 +540,11 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
                            ps.d_items, ps.nitems, f, plan->ws);
       break;
     case kFused:
-      e = launch_fused_z(plan->cfg.precision, plan->ndim, plan->cfg.source_mode, ps.mpt, ps.shape,
+      e = launch_fused_z(plan->cfg.precision, plan->ndim, plan->src_form, ps.mpt, ps.shape,
                          s, plan->d_patches, ps.d_items, ps.nitems, plan->ws, ph);
       break;
     case kUpdate:
-      e = launch_update(plan->cfg.precision, plan->cfg.source_mode, ps.shape, s, plan->d_patches,
+      e = launch_update(plan->cfg.precision, plan->src_form, ps.shape, s, plan->d_patches,
                         ps.d_items, ps.nitems, plan->ws, ph);
       break;
     case kFastXFwd:
@@ -696,6 +739,9 @@ psatd_status build_plan(psatd_plan_s* plan) {
   const psatd_config& cfg = plan->cfg;
   plan->ndim = plan->desc[0].ndim;
   plan->nin = inputs_for(cfg.source_mode);
+  const bool pstd = (cfg.flags & PSATD_FLAG_PSTD) != 0;
+  plan->src_form = !pstd ? cfg.source_mode
+                         : (cfg.source_mode == PSATD_VACUUM ? kPstdVacuum : kPstdJ);
   plan->elem = cfg.precision == PSATD_FP32 ? 4 : 8;
 
   // ---- tables layout (bytes): per patch kx, ky, kz, post; per FFT length twiddles
@@ -884,10 +930,11 @@ psatd_status build_plan(psatd_plan_s* plan) {
 
   char buf[512];
   plan->info.clear();
-  std::snprintf(buf, sizeof(buf), "ndim=%d patches=%zu precision=%s source=%d path=%s order=%d ws=%zu\n",
-                plan->ndim, plan->host_patches.size(), cfg.precision == PSATD_FP32 ? "fp32" : "fp64",
-                cfg.source_mode, cfg.path == PSATD_PATH_FUSED ? "fused" : "plain", cfg.order,
-                plan->ws_bytes);
+  std::snprintf(buf, sizeof(buf),
+                "ndim=%d patches=%zu solver=%s precision=%s source=%d path=%s order=%d ws=%zu\n",
+                plan->ndim, plan->host_patches.size(), pstd ? "pstd" : "psatd",
+                cfg.precision == PSATD_FP32 ? "fp32" : "fp64", cfg.source_mode,
+                cfg.path == PSATD_PATH_FUSED ? "fused" : "plain", cfg.order, plan->ws_bytes);
   plan->info += buf;
   for (const Pass& ps : plan->passes) {
     std::snprintf(buf, sizeof(buf),

@@ -14,7 +14,7 @@ struct Group;
 // 2D s-polarization
 template <int SRC>
 struct Group<0, SRC> {
-  static constexpr int nin = (SRC == kVacuum) ? 3 : 4;
+  static constexpr int nin = src_has_j(SRC) ? 4 : 3;
   static constexpr int in[4] = {kEy, kBx, kBz, kJy};
   static constexpr int nout = 3;
   static constexpr int out_slot[3] = {0, 1, 2};
@@ -22,7 +22,7 @@ struct Group<0, SRC> {
 // 2D p-polarization
 template <int SRC>
 struct Group<1, SRC> {
-  static constexpr int nin = (SRC == kVacuum) ? 3 : (SRC == kJForm ? 5 : 7);
+  static constexpr int nin = !src_has_j(SRC) ? 3 : (SRC == kRho ? 7 : 5);
   static constexpr int in[7] = {kEx, kEz, kBy, kJx, kJz, kRhoOld, kRhoNew};
   static constexpr int nout = 3;
   static constexpr int out_slot[3] = {0, 1, 2};
@@ -30,7 +30,7 @@ struct Group<1, SRC> {
 // 3D: everything couples
 template <int SRC>
 struct Group<2, SRC> {
-  static constexpr int nin = (SRC == kVacuum) ? 6 : (SRC == kJForm ? 9 : 11);
+  static constexpr int nin = !src_has_j(SRC) ? 6 : (SRC == kRho ? 11 : 9);
   static constexpr int in[11] = {kEx, kEy, kEz, kBx, kBy, kBz, kJx, kJy, kJz, kRhoOld, kRhoNew};
   static constexpr int nout = 6;
   static constexpr int out_slot[6] = {0, 1, 2, 3, 4, 5};

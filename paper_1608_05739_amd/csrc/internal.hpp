@@ -15,7 +15,11 @@ enum Comp : int {
   kEx = 0, kEy, kEz, kBx, kBy, kBz, kJx, kJy, kJz, kRhoOld, kRhoNew
 };
 
-enum SourceForm : int { kVacuum = 0, kRho = 1, kJForm = 2 };
+// Update forms: the PSATD step in vacuum, with sources in the rho form or in
+// the J form, and the PSTD leapfrog contrast solver (vacuum or J).
+enum SourceForm : int { kVacuum = 0, kRho = 1, kJForm = 2, kPstdVacuum = 3, kPstdJ = 4 };
+constexpr bool src_is_pstd(int s) { return s == kPstdVacuum || s == kPstdJ; }
+constexpr bool src_has_j(int s) { return s == kRho || s == kJForm || s == kPstdJ; }
 
 // A complex FFT of length n factorized into radices (applied in order,
 // Stockham autosort).  tw[m] = exp(-2 pi i m / n) in FP64, m in [0, n).

@@ -272,8 +272,6 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
         ky = P->ky[line % P->ny];
       }
       const double kz = P->kz[iz];
-      const double K = sqrt(kx * kx + ky * ky + kz * kz);
-      const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
       double2 E[3] = {}, B[3] = {}, J[3] = {};
       double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
       static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
@@ -287,7 +285,13 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
         else rn = v;
       });
       double2 Eo[3], Bo[3];
-      update_mode<SRC>(kx, ky, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+      if constexpr (src_is_pstd(SRC)) {
+        pstd_update_mode<SRC>(kx, ky, kz, dt, ph.c, ph.eps0, P->inv_n, E, B, J, Eo, Bo);
+      } else {
+        const double K = sqrt(kx * kx + ky * ky + kz * kz);
+        const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
+        update_mode<SRC>(kx, ky, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+      }
       static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
         constexpr int o = decltype(oc)::value;
         constexpr int comp = Gr::in[Gr::out_slot[o]];
@@ -364,8 +368,6 @@ update_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__
         ky = P->ky[line % P->ny];
       }
       const double kz = P->kz[iz];
-      const double K = sqrt(kx * kx + ky * ky + kz * kz);
-      const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
       double2 E[3], B[3], J[3] = {};
       double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
 #pragma unroll
@@ -373,7 +375,7 @@ update_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__
         E[i] = to_d2(base[(kEx + i) * cs + idx]);
         B[i] = to_d2(base[(kBx + i) * cs + idx]);
       }
-      if constexpr (SRC != kVacuum) {
+      if constexpr (src_has_j(SRC)) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) J[i] = to_d2(base[(kJx + i) * cs + idx]);
       }
@@ -382,7 +384,13 @@ update_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__
         rn = to_d2(base[kRhoNew * cs + idx]);
       }
       double2 Eo[3], Bo[3];
-      update_mode<SRC>(kx, ky, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+      if constexpr (src_is_pstd(SRC)) {
+        pstd_update_mode<SRC>(kx, ky, kz, dt, ph.c, ph.eps0, P->inv_n, E, B, J, Eo, Bo);
+      } else {
+        const double K = sqrt(kx * kx + ky * ky + kz * kz);
+        const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
+        update_mode<SRC>(kx, ky, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+      }
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         base[(kEx + i) * cs + idx] = from_d2<V>(Eo[i]);
@@ -492,6 +500,14 @@ static hipError_t fused_dispatch(int src, const LaunchShape& sh, hipStream_t str
       hipLaunchKernelGGL((fused_z_kernel<S, DIM, kRho, MPT>), dim3(sh.grid), dim3(sh.block),
                          sh.lds_bytes, stream, p, it, n, ws, ph);
       break;
+    case kPstdVacuum:
+      hipLaunchKernelGGL((fused_z_kernel<S, DIM, kPstdVacuum, MPT>), dim3(sh.grid),
+                         dim3(sh.block), sh.lds_bytes, stream, p, it, n, ws, ph);
+      break;
+    case kPstdJ:
+      hipLaunchKernelGGL((fused_z_kernel<S, DIM, kPstdJ, MPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, ws, ph);
+      break;
     default:
       hipLaunchKernelGGL((fused_z_kernel<S, DIM, kJForm, MPT>), dim3(sh.grid), dim3(sh.block),
                          sh.lds_bytes, stream, p, it, n, ws, ph);
@@ -529,6 +545,14 @@ static hipError_t update_dispatch(int src, const LaunchShape& sh, hipStream_t st
     case kRho:
       hipLaunchKernelGGL((update_kernel<S, kRho>), dim3(sh.grid), dim3(sh.block), 0, stream, p, it,
                          n, ws, ph);
+      break;
+    case kPstdVacuum:
+      hipLaunchKernelGGL((update_kernel<S, kPstdVacuum>), dim3(sh.grid), dim3(sh.block), 0, stream,
+                         p, it, n, ws, ph);
+      break;
+    case kPstdJ:
+      hipLaunchKernelGGL((update_kernel<S, kPstdJ>), dim3(sh.grid), dim3(sh.block), 0, stream, p,
+                         it, n, ws, ph);
       break;
     default:
       hipLaunchKernelGGL((update_kernel<S, kJForm>), dim3(sh.grid), dim3(sh.block), 0, stream, p,
@@ -591,6 +615,8 @@ static hipError_t set_fused_attrs() {
   set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kVacuum, MPT>));
   set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kRho, MPT>));
   set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kJForm, MPT>));
+  set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kPstdVacuum, MPT>));
+  set(reinterpret_cast<const void*>(&fused_z_kernel<S, DIM, kPstdJ, MPT>));
   return e;
 }
 

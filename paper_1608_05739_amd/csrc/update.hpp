@@ -173,6 +173,38 @@ __device__ __forceinline__ void update_mode(const double kx, const double ky, co
   }
 }
 
+// PSTD leapfrog step of one mode (Table 1, PSTD row: spectral derivatives,
+// finite differences in time), the contrast solver.  B is at half-integer
+// times:
+//   B' = B - i dt (k x E),   E' = E + i c^2 dt (k x B') - (dt/eps0) J
+// and both results are multiplied by `scale`.
+template <int SRC>
+__device__ __forceinline__ void pstd_update_mode(const double kx, const double ky,
+                                                 const double kz, double dt, double c,
+                                                 double eps0, double scale, const double2* E,
+                                                 const double2* B, const double2* J, double2* Eo,
+                                                 double2* Bo) {
+  const double2 kxE[3] = {
+      csub(cscale(E[2], ky), cscale(E[1], kz)),
+      csub(cscale(E[0], kz), cscale(E[2], kx)),
+      csub(cscale(E[1], kx), cscale(E[0], ky))};
+  double2 Bn[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Bn[i] = csub(B[i], i_times(kxE[i], dt));
+  const double2 kxB[3] = {
+      csub(cscale(Bn[2], ky), cscale(Bn[1], kz)),
+      csub(cscale(Bn[0], kz), cscale(Bn[2], kx)),
+      csub(cscale(Bn[1], kx), cscale(Bn[0], ky))};
+  const double cdt = c * c * dt;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double2 e = cadd(E[i], i_times(kxB[i], cdt));
+    if constexpr (SRC == kPstdJ) e = csub(e, cscale(J[i], dt / eps0));
+    Eo[i] = cscale(e, scale);
+    Bo[i] = cscale(Bn[i], scale);
+  }
+}
+
 // ------------------------------------------------------------------ 2D forms
 // In 2D (k_y = 0) the update splits into two independent sets:
 //   s-polarization (Ey, Bx, Bz; Jy):

@@ -135,3 +135,52 @@ def test_domain_validation_on_host(lib, dom, expect):
     assert st == expect
     assert h.value is None
     assert lib.psatd_last_error().decode()
+
+
+@pytest.mark.parametrize("desc,cfg,expect", [
+    (_desc(), _cfg(flags=b.FLAG_PSTD, source_mode=1), -1),   # PSTD takes J only
+    (_desc(dt=0.7), _cfg(flags=b.FLAG_PSTD), -1),            # c dt |k|max / 2 = 1.18 > 1
+    (_desc(dt=0.6), _cfg(flags=b.FLAG_PSTD), None),          # 0.5 * 0.6 * 2 pi 3/8 sqrt 2 = 0.9996
+])
+def test_pstd_validation_on_host(lib, desc, cfg, expect):
+    out = ctypes.c_void_p()
+    st = lib.psatd_plan(ctypes.byref(cfg), ctypes.byref(desc), 1, 0, ctypes.byref(out))
+    if expect is None:
+        # valid: fails only at the device query without a GPU
+        assert st in (0, -4), lib.psatd_last_error().decode()
+        if st == 0:
+            lib.psatd_destroy(out)
+    else:
+        assert st == expect, lib.psatd_last_error().decode()
+        assert out.value is None
+
+
+@pytest.mark.parametrize("scheme,desc,cfg,expect", [
+    (5, _desc(), _cfg(), -1),                                   # unknown scheme
+    (0, _desc(), _cfg(source_mode=1), -1),                      # rho form: FDTD takes J only
+    (0, _desc(), _cfg(order=3), -1),                            # odd order
+    (0, _desc(), _cfg(order=34), -1),                           # beyond 32
+    (0, _desc(), _cfg(flags=b.FLAG_GRAPH), -1),                 # flags must be 0
+    (1, _desc(), _cfg(order=4), -1),                            # CKC is second order
+    (1, _desc(n=(8, 8, 8), ndim=3), _cfg(), -2),                # CKC in 3D
+    (1, _desc(d=(1.0, 1.0, 0.5), dt=0.4), _cfg(), -1),          # CKC needs dx = dz
+    (0, _desc(dt=0.75), _cfg(), -1),                            # Yee 2D: c dt <= dx / sqrt 2
+    (0, _desc(n=(8, 1, 8), dt=0.1), _cfg(order=16), -2),        # n < p
+    (0, _desc(n=(8, 1, 8), dt=0.1, offset=-1), _cfg(), -1),
+    (1, _desc(dt=1.0), _cfg(), None),                           # CKC at c dt = dx: allowed
+    (0, _desc(dt=0.7071), _cfg(), None),                        # Yee just below 1/sqrt 2
+    (0, _desc(n=(5, 1, 7), dt=0.3), _cfg(), None),              # any length
+])
+def test_fdtd_validation_on_host(lib, scheme, desc, cfg, expect):
+    out = ctypes.c_void_p()
+    st = lib.psatd_fdtd_plan(ctypes.byref(cfg), scheme, ctypes.byref(desc), 0, ctypes.byref(out))
+    if expect is None:
+        assert st in (0, -4), lib.psatd_last_error().decode()
+        if st == 0:
+            lib.psatd_fdtd_destroy(out)
+    else:
+        assert st == expect, lib.psatd_last_error().decode()
+        assert out.value is None
+        assert lib.psatd_last_error().decode()
+    assert lib.psatd_fdtd_push(None, None, 1, None) == -1
+    assert lib.psatd_fdtd_destroy(None) == 0
