@@ -286,6 +286,88 @@ def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
     print(json.dumps(out), flush=True)
 
 
+def bench_contrast(pk, args):
+    """The contrast solvers of Table 1 beside PSATD on the workload's grid
+    (FP32 storage, J sources, each at its Courant-limited time step): ms per
+    step, cell-steps/s, the model's HBM bytes, and the cost ratio of PSATD
+    to each (the paper's xi, per step at equal resolution, Sec. IV.C)."""
+    import torch
+
+    steps = args.steps or 200
+    warm = min(args.warmup, 10)
+    w = build_inputs(args.workload, steps)
+    p = w.patches[0]
+    if p.ndim != 2 or not w.sources:
+        raise SystemExit("--contrast times the 2D workload with sources (workload 1)")
+    cells = w.cells
+    dx = p.dx
+    out = {"metric": "field-step time of PSATD and the contrast solvers (Table 1), 1 GPU",
+           "unit": "ms/step", "n_gpus": 1, "steps": steps, "warmup": warm, "dtype": "f64",
+           "config": {"workload": w.name, "storage": "f32", "sources": "J"}, "solvers": {}}
+
+    def record(name, sec, dt, bytes_per_cell, kernels):
+        ms = 1e3 * sec / steps
+        out["solvers"][name] = {"ms_per_step": ms, "cell_steps_per_s": cells * steps / sec,
+                                "dt_over_dx": dt / dx, "model_bytes_per_cell": bytes_per_cell,
+                                "model_GBps": bytes_per_cell * cells / (ms * 1e-3) / 1e9,
+                                "kernels": kernels}
+        log(f"[bench] {name}: {ms:.3f} ms/step")
+
+    def psatd_like(name, mode, dt, **kw):
+        pp = fixtures_patch(p, dt)
+        plan = pk.Plan([pp], precision="fp32", source_mode=mode, path="fused", graph=True,
+                       autotune=True, **kw)
+        E, B, J, ro, rn = device_fields(w, plan, np.float32)
+        if mode == "j":
+            ro = rn = None
+        sec = time_steps(plan, E, B, J, ro, rn, steps, warm, False)
+        nin = 11 if mode == "rho" else 9
+        record(name, sec, dt, 4 * (2 * nin + (nin + 6) + 2 * 6), plan.pass_names)
+        plan.close()
+        del E, B, J, ro, rn
+
+    def fdtd(name, scheme, dt):
+        pp = fixtures_patch(p, dt)
+        f = pk.Fdtd(scheme, pp, precision="fp32", source_mode="j")
+        plan_like = type("P", (), {"total_elements": cells, "offsets": [0]})
+        E, B, J, _, _ = device_fields(w, plan_like, np.float32)
+
+        def run(n):
+            for _ in range(n):
+                f.push(E, B, J)
+        run(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        # Faraday: E, B in, B out; Ampere: B, E, J in, E out
+        record(name, sec, dt, 4 * ((6 + 3) + (9 + 3)), ["faraday", "ampere"])
+        f.close()
+        del E, B, J
+
+    psatd_like("psatd_rho", "rho", p.dt)
+    psatd_like("psatd_j", "j", p.dt)
+    psatd_like("psatd_j_generic", "j", p.dt, generic_kernels=True)
+    psatd_like("pstd", "j", np.sqrt(2.0) / np.pi * dx, pstd=True)
+    fdtd("yee", "yee", dx / np.sqrt(2.0))
+    fdtd("ckc", "ckc", dx)
+    t = {k: v["ms_per_step"] for k, v in out["solvers"].items()}
+    out["xi_psatd_over_yee"] = t["psatd_rho"] / t["yee"]
+    out["xi_psatd_over_ckc"] = t["psatd_rho"] / t["ckc"]
+    out["pstd_over_psatd_j_generic"] = t["pstd"] / t["psatd_j_generic"]
+    # cost per unit of simulated time, each at its own Courant-limited dt
+    out["cost_per_sim_time_vs_psatd"] = {
+        k: (v["ms_per_step"] / v["dt_over_dx"]) / (t["psatd_rho"] / out["solvers"]["psatd_rho"]["dt_over_dx"])
+        for k, v in out["solvers"].items()}
+    print(json.dumps(out), flush=True)
+
+
+def fixtures_patch(p, dt):
+    import fixtures
+    return fixtures.workloads.Patch(p.ndim, p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, float(dt))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +384,9 @@ def main():
     ap.add_argument("--decomposition", action="store_true",
                     help="instead of the default line: time the guard-cell domain decomposition "
                          "(2 x 2 boxes, 128 guard cells, centered order 16) on the same workload")
+    ap.add_argument("--contrast", action="store_true",
+                    help="instead of the default line: time PSATD beside the contrast solvers "
+                         "(PSTD, Yee, CKC) on the workload's grid")
     ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: store HBM bytes per pass from two rocprofv3 --pmc counter "
                          "files (FETCH_SIZE, WRITE_SIZE) of this script, scaled by its "
@@ -333,6 +418,8 @@ def main():
     index = args.workload
     if args.decomposition:
         return bench_decomposition(pk, args)
+    if args.contrast:
+        return bench_contrast(pk, args)
     default_steps = {0: 100, 1: 1000, 2: 200, 3: 500, 4: 100}[index]
     steps = args.steps if args.steps is not None else default_steps
     w = build_inputs(index, steps)
