@@ -554,8 +554,8 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
       e = fast2d::launch_x_inv(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
       break;
     default:
-      e = fast2d::launch_z_fused(plan->cfg.source_mode, ps.shape, s, plan->d_patches, ps.d_items,
-                                 ps.nitems, plan->ws, ph);
+      e = fast2d::launch_z_fused(plan->cfg.source_mode, plan->cfg.order == 0, ps.shape, s,
+                                 plan->d_patches, ps.d_items, ps.nitems, plan->ws, ph);
       break;
   }
   if (e != hipSuccess) return hip_fail(e, ps.name);
@@ -821,6 +821,8 @@ psatd_status build_plan(psatd_plan_s* plan) {
     P.mx = P.nx / 2;
     P.dt = d.dt;
     P.inv_n = 1.0 / (static_cast<double>(P.nx) * P.ny * P.nz);
+    P.dkz = cfg.order == 0 ? 6.283185307179586476925286766559 / (static_cast<double>(P.nz) * d.d[2])
+                           : 0.0;
     P.off_real = d.offset;
     P.comp_stride = static_cast<long long>(P.mx) * P.ny * P.nz;
     P.off_spec = spec_off;

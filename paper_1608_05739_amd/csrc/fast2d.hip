@@ -50,6 +50,43 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 4 x 4 transpose of 16-byte chunks across the lanes l, l + 16, l + 32,
+// l + 48 of a wave (l < 16): on return, chunk j of lane l + 16 a holds what
+// chunk a of lane l + 16 j held.  Two register-only lane swaps per dword
+// (v_permlane32_swap exchanges the lane bit of weight 32 with the chunk bit
+// of weight 2, v_permlane16_swap the lane bit 16 with the chunk bit 1).
+// The workspace columns lie 32 KB apart, so a wave whose 64 lanes each
+// touch a different column translates 64 addresses per instruction; after
+// the transpose four lanes share a column and an instruction touches 16.
+__device__ __forceinline__ void quad_transpose(float4 (&c)[4]) {
+  auto swap32 = [](float& x, float& y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y),
+                                                    false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+  };
+  auto swap16 = [](float& x, float& y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y),
+                                                    false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+  };
+#pragma unroll
+  for (int j0 = 0; j0 < 2; ++j0) {
+    swap32(c[j0].x, c[2 + j0].x);
+    swap32(c[j0].y, c[2 + j0].y);
+    swap32(c[j0].z, c[2 + j0].z);
+    swap32(c[j0].w, c[2 + j0].w);
+  }
+#pragma unroll
+  for (int j1 = 0; j1 < 4; j1 += 2) {
+    swap16(c[j1].x, c[j1 + 1].x);
+    swap16(c[j1].y, c[j1 + 1].y);
+    swap16(c[j1].z, c[j1 + 1].z);
+    swap16(c[j1].w, c[j1 + 1].w);
+  }
+}
+
 // Exchange 32 complex values through a wave region: value (b, q) is written at
 // padded index widx(b, q) and value (b', q') is read back from ridx(b', q').
 // The index functions return padx() of the logical index written as a per-lane
@@ -239,13 +276,23 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
         if (kx == 0) X[r] = make_double2(za.x + za.y, za.x - za.y);
       }
       DFT<8, -1>::run(X);
-      float4* dst = reinterpret_cast<float4*>(out + (long long)kx * kNZ + 8 * z1);
+      float4 ch[4];
 #pragma unroll
       for (int k2 = 0; k2 < 8; k2 += 2) {
         const double2 u = cmul(X[k2], tz[k2]);
         const double2 v = cmul(X[k2 + 1], tz[k2 + 1]);
-        dst[k2 / 2] = make_float4(static_cast<float>(u.x), static_cast<float>(u.y),
-                                  static_cast<float>(v.x), static_cast<float>(v.y));
+        ch[k2 / 2] = make_float4(static_cast<float>(u.x), static_cast<float>(u.y),
+                                 static_cast<float>(v.x), static_cast<float>(v.y));
+      }
+      // lane l + 16 a now stores chunk a (k2 = 2a, 2a + 1) of the columns of
+      // lanes l + 16 j, j = 0..3: 16 columns per store instead of 64
+      quad_transpose(ch);
+      const int lq = l & 15, aq = l >> 4;
+      const long long kx0 = kx - l + lq;  // the column of lane lq (j = 0)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float4* dst = reinterpret_cast<float4*>(out + (kx0 + 16 * j) * kNZ + 8 * z1) + aq;
+        *dst = ch[j];
       }
       wk = cmul(wk, wstep);
     }
@@ -274,13 +321,21 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 #pragma unroll 1
     for (int i = 0; i < 4; ++i) {
       const int kx = threadIdx.x + 512 * i;
-      const float4* src = reinterpret_cast<const float4*>(in + (long long)kx * kNZ + 8 * z1);
+      // lane l + 16 a loads chunk a of the columns of lanes l + 16 j (16
+      // columns per load instead of 64); the transpose then hands every lane
+      // the four chunks of its own column
+      const int lq = l & 15, aq = l >> 4;
+      const long long kx0 = kx - l + lq;
+      float4 ch[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        ch[j] = *(reinterpret_cast<const float4*>(in + (kx0 + 16 * j) * kNZ + 8 * z1) + aq);
+      quad_transpose(ch);
       double2 X[8];
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const float4 v = src[h];
-        X[2 * h] = make_double2(v.x, v.y);
-        X[2 * h + 1] = make_double2(v.z, v.w);
+        X[2 * h] = make_double2(ch[h].x, ch[h].y);
+        X[2 * h + 1] = make_double2(ch[h].z, ch[h].w);
       }
       DFT<8, 1>::run(X);
 #pragma unroll
@@ -360,6 +415,25 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
 constexpr int kGroupStride = 513;
 constexpr int kZBuf = kGroupStride * 7 + 512;  // double2 per transition buffer
 
+// After the transition buffers and the coefficient slots, LDS holds the
+// twiddles every thread uses in every transform, read from the FP64 table
+// once per workgroup: a global load inside a transform would be issued after
+// the prefetch of the next input, and since loads complete in order, waiting
+// for it would wait for the prefetch.
+constexpr int kZtS2 = 0;      // W4096^(64 k), k < 8: stage-2 bases (k = jB mod 8)
+constexpr int kZtS3 = 8;      // W4096^(8 j), j < 64: stage-3 bases (j = jB)
+constexpr int kZtOut = 72;    // W4096^(jA k2A) of thread tA: first output twiddle of an inverse
+constexpr int kZtStep = 584;  // W4096^(64 k2), k2 < 8: its step over q
+constexpr int kZtCount = 592;
+
+// One twiddle from the LDS table at an index the optimizer cannot see through,
+// so that every transform reads it again (reuse across transforms would keep
+// the bases and their powers live through the whole kernel).
+__device__ __forceinline__ double2 zt_read(const double2* zt, int idx) {
+  asm volatile("" : "+v"(idx));
+  return zt[idx];
+}
+
 template <int SIGN>
 __device__ __forceinline__ void twiddle8(double2 (&v)[8], double2 w) {
   if constexpr (SIGN > 0) w.y = -w.y;
@@ -398,11 +472,11 @@ __device__ __forceinline__ ZIdx make_zidx() {
 
 // Forward: v holds elements jA + 64 q of group k2A (mapping A) on entry and
 // transform outputs jB + 64 q of group k2B (mapping B) on exit.  The twiddle
-// bases are read from the table inside each call, after a barrier: otherwise
-// the compiler would keep the powers of the (identical) bases of every call
-// live across the whole kernel.
+// bases are read from LDS inside each call, after a barrier: otherwise the
+// compiler would keep the powers of the (identical) bases of every call live
+// across the whole kernel.
 __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx& x,
-                                       const double2* __restrict__ tw4096) {
+                                       const double2* zt) {
   DFT<8, -1>::run(v);  // stage 1 (Ns = 1), mapping A; outputs 8 j + q
   double2* wa = buf + x.baseA;
 #pragma unroll
@@ -413,7 +487,7 @@ __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = b1[64 * q];
   // stage 2: Ns = 8, k = j mod 8, w = exp(-2 pi i k / 64); outputs 8 (j - k) + k + 8 q
-  twiddle8<-1>(v, tw4096[64 * (x.jB & 7)]);
+  twiddle8<-1>(v, zt_read(zt, kZtS2 + (x.jB & 7)));
   DFT<8, -1>::run(v);
 #pragma unroll
   for (int q = 0; q < 8; ++q) b2[8 * q] = v[q];
@@ -421,7 +495,7 @@ __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = b1[64 * q];
   // stage 3: Ns = 64, k = j, w = exp(-2 pi i j / 512); outputs j + 64 q
-  twiddle8<-1>(v, tw4096[8 * x.jB]);
+  twiddle8<-1>(v, zt_read(zt, kZtS3 + x.jB));
   DFT<8, -1>::run(v);
 }
 
@@ -429,12 +503,12 @@ __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx
 // group k2B (mapping B) on entry and elements jA + 64 q of group k2A
 // (mapping A) on exit.
 __device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx& x,
-                                       const double2* __restrict__ tw4096) {
+                                       const double2* zt) {
   double2* b1 = buf + x.baseB1;
   double2* b2 = buf + x.baseB2;
   // adjoint of stage 3
   DFT<8, 1>::run(v);
-  twiddle8<1>(v, tw4096[8 * x.jB]);  // conjugate twiddles after the butterflies
+  twiddle8<1>(v, zt_read(zt, kZtS3 + x.jB));  // conjugate twiddles after the butterflies
 #pragma unroll
   for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
   wave_lds_sync();
@@ -442,7 +516,7 @@ __device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx
   for (int q = 0; q < 8; ++q) v[q] = b2[8 * q];
   // adjoint of stage 2
   DFT<8, 1>::run(v);
-  twiddle8<1>(v, tw4096[64 * (x.jB & 7)]);
+  twiddle8<1>(v, zt_read(zt, kZtS2 + (x.jB & 7)));
 #pragma unroll
   for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
   __syncthreads();
@@ -465,12 +539,16 @@ __device__ __forceinline__ void z_load(const float2* src, float2 (&raw)[8], int 
 
 // Per-column state of the z pass.  The transforms alternate between the two
 // transition buffers: `tr` counts them (uniform across the workgroup).
+// EXACT: the k tables hold the exact wavenumbers, so kz follows from the mode
+// index; otherwise (order p) kz is read from the table.
+template <bool EXACT>
 struct ZCol {
   float2* col;       // workspace spectrum of column kx, component 0
   long long cs;      // component stride (complex elements)
   double kx, dt, c, c2, eps0, ie, scale;
-  const double* kzb; // kz in mapping-B order
-  const double2* tw; // exp(-2 pi i m / 4096)
+  double dkz;        // 2 pi / (nz dz) for the exact wavenumbers, else 0
+  const double* kzb; // kz in mapping-B order (order-p tables)
+  const double2* zt; // the twiddles in LDS (kZt*)
   ZIdx x;
   double2* lds;      // two transition buffers of kZBuf double2
   int tr;
@@ -480,12 +558,23 @@ struct ZCol {
     ++tr;
     return b;
   }
-  // The empty asm makes every read of kz opaque to the optimizer: the s and p
-  // groups evaluate the same coefficients, and merging the two evaluations
-  // would keep them live across the s group's inverse transforms.
+  // kz of mode 8 jB + k2B + 512 q.  Exact wavenumbers come from the index, as
+  // the k table computes them (a global load here would wait for the
+  // prefetch, see kZt*); order-p tables are read.  The empty asm makes every
+  // kz opaque to the optimizer: the s and p groups evaluate the same
+  // coefficients, and merging the two evaluations would keep them live
+  // across the s group's inverse transforms.
   __device__ __forceinline__ double kz_of(int q) const {
-    const double* __restrict__ kzq = kzb + 512 * q;
-    double v = kzq[x.tB];
+    int o = 512 * q;
+    asm volatile("" : "+v"(o));
+    double v;
+    if constexpr (EXACT) {
+      const int idx = 8 * x.jB + x.k2B + o;
+      const int m = idx < kNZ / 2 ? idx : (idx == kNZ / 2 ? 0 : idx - kNZ);
+      v = static_cast<double>(m) * dkz;
+    } else {
+      v = kzb[x.tB + o];
+    }
     asm volatile("" : "+v"(v));
     return v;
   }
@@ -502,7 +591,7 @@ struct ZCol {
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = ld2(pre[q]);
     z_load(next, pre, x.tA);
-    fwd512(v, next_buf(), x, tw);
+    fwd512(v, next_buf(), x, zt);
 #pragma unroll
     for (int q = 0; q < 8; ++q) dst[q] = st2(v[q]);
     // keep the transform's temporaries apart from the update that follows
@@ -514,9 +603,9 @@ struct ZCol {
     double2 v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = ld2(src_b[q]);
-    inv512(v, next_buf(), x, tw);
-    double2 tq = cconj(tw[(x.jA * x.k2A) & (kNZ - 1)]);
-    const double2 step = cconj(tw[(64 * x.k2A) & (kNZ - 1)]);
+    inv512(v, next_buf(), x, zt);
+    double2 tq = cconj(zt_read(zt, kZtOut + x.tA));
+    const double2 step = cconj(zt_read(zt, kZtStep + x.k2A));
     float2* dst = col + comp * cs;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -527,9 +616,10 @@ struct ZCol {
   }
 };
 
-__device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* ws,
+template <bool EXACT>
+__device__ __forceinline__ ZCol<EXACT> make_zcol(const PatchDev* P, int kxcol, float* ws,
                                           const Physics& ph, double2* lds, int tr) {
-  ZCol z;
+  ZCol<EXACT> z;
   z.col = reinterpret_cast<float2*>(ws) + P->off_spec + (long long)kxcol * kNZ;
   z.cs = P->comp_stride;
   z.kx = P->kx[kxcol];
@@ -539,8 +629,9 @@ __device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* w
   z.eps0 = ph.eps0;
   z.ie = 1.0 / ph.eps0;
   z.scale = P->inv_n;
+  z.dkz = P->dkz;
   z.kzb = P->kz_b;
-  z.tw = P->fz.tw;
+  z.zt = lds + 2 * kZBuf + kNZ / 4;
   z.x = make_zidx();
   z.lds = lds;
   z.tr = tr;
@@ -562,8 +653,8 @@ __device__ __forceinline__ ZCol make_zcol(const PatchDev* P, int kxcol, float* w
 //   Ex: Ex' += C Ex,  By' -= i S kz Ex
 //   Ez: Ez' += C Ez,  By' += i S kx Ez
 // (p-pol with sources: z_ppol_sources.)
-template <int G, int SRC>
-__device__ __forceinline__ void z_group(ZCol& z, float2 (&pre)[8], const float2* next) {
+template <int G, int SRC, typename Z>
+__device__ __forceinline__ void z_group(Z& z, float2 (&pre)[8], const float2* next) {
   static_assert(G == 0 || SRC == kVacuum, "p-pol with sources has its own schedule");
   constexpr bool kSrc = SRC != kVacuum;
   constexpr int kO0 = G == 0 ? kEy : kEx;
@@ -705,8 +796,8 @@ __device__ __forceinline__ void z_group(ZCol& z, float2 (&pre)[8], const float2*
 //              By: field terms as in vacuum
 //              Ex: Ex' += C Ex + L1 kx kx Ex, Ez' += L1 kz kx Ex, By' -= i S kz Ex
 //              Ez: Ez' += C Ez + L1 kz kz Ez, Ex' += L1 kx kz Ez, By' += i S kx Ez
-template <int SRC>
-__device__ __forceinline__ void z_ppol_sources(ZCol& z, float* cx, float2 (&pre)[8],
+template <int SRC, typename Z>
+__device__ __forceinline__ void z_ppol_sources(Z& z, float* cx, float2 (&pre)[8],
                                                const float2* next) {
   static_assert(SRC == kRho || SRC == kJForm, "source forms only");
   const double kx = z.kx, c2 = z.c2;
@@ -875,7 +966,7 @@ struct ZOrder {
   static constexpr int kFirstP = SRC == kVacuum ? kBy : (SRC == kRho ? kRhoOld : kJx);
 };
 
-template <int SRC>
+template <int SRC, bool EXACT>
 __global__ void __launch_bounds__(512)
 z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
                int nitems, float* __restrict__ ws, Physics ph) {
@@ -885,12 +976,26 @@ z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict_
   int it = blockIdx.x;
   if (it >= nitems) return;
   int patch = items[it].patch, kxcol = items[it].first;
+  {
+    // every patch of this pass has nz = 4096 and shares the FP64 table
+    const double2* __restrict__ tw = patches[patch].fz.tw;
+    double2* zt = lds2 + 2 * kZBuf + kNZ / 4;
+    for (int e = threadIdx.x; e < kZtCount; e += blockDim.x) {
+      int m;
+      if (e < kZtS3) m = 64 * (e - kZtS2);
+      else if (e < kZtOut) m = 8 * (e - kZtS3);
+      else if (e < kZtStep) m = (((e - kZtOut) >> 3) * ((e - kZtOut) & 7)) & (kNZ - 1);
+      else m = (64 * (e - kZtStep)) & (kNZ - 1);
+      zt[e] = tw[m];
+    }
+    __syncthreads();
+  }
   float2 pre[8];
-  z_load(make_zcol(patches + patch, kxcol, ws, ph, lds2, 0).src(ZOrder<SRC>::kFirstS), pre,
+  z_load(make_zcol<EXACT>(patches + patch, kxcol, ws, ph, lds2, 0).src(ZOrder<SRC>::kFirstS), pre,
          threadIdx.x);
   int tr = 0;  // transforms done so far: selects the transition buffer
   for (; it < nitems; it += gridDim.x) {
-    ZCol z = make_zcol(patches + patch, kxcol, ws, ph, lds2, tr);
+    ZCol<EXACT> z = make_zcol<EXACT>(patches + patch, kxcol, ws, ph, lds2, tr);
     // The p group's last phase prefetches the next column's first input; after
     // the last column it re-reads this column's (never used).
     const int nit = it + gridDim.x;
@@ -926,23 +1031,30 @@ hipError_t launch_x_inv(const LaunchShape& sh, hipStream_t s, const PatchDev* p,
   return hipGetLastError();
 }
 
-hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t s, const PatchDev* p,
-                          const WorkItem* it, int n, void* ws, Physics ph) {
-  float* w = static_cast<float*>(ws);
+template <bool EXACT>
+static void launch_z(int src, const LaunchShape& sh, hipStream_t s, const PatchDev* p,
+                     const WorkItem* it, int n, float* w, Physics ph) {
   switch (src) {
     case kVacuum:
-      hipLaunchKernelGGL(z_fused_kernel<kVacuum>, dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s,
-                         p, it, n, w, ph);
+      hipLaunchKernelGGL((z_fused_kernel<kVacuum, EXACT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, s, p, it, n, w, ph);
       break;
     case kRho:
-      hipLaunchKernelGGL(z_fused_kernel<kRho>, dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s, p,
-                         it, n, w, ph);
+      hipLaunchKernelGGL((z_fused_kernel<kRho, EXACT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, s, p, it, n, w, ph);
       break;
     default:
-      hipLaunchKernelGGL(z_fused_kernel<kJForm>, dim3(sh.grid), dim3(sh.block), sh.lds_bytes, s,
-                         p, it, n, w, ph);
+      hipLaunchKernelGGL((z_fused_kernel<kJForm, EXACT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, s, p, it, n, w, ph);
       break;
   }
+}
+
+hipError_t launch_z_fused(int src, bool exact_k, const LaunchShape& sh, hipStream_t s,
+                          const PatchDev* p, const WorkItem* it, int n, void* ws, Physics ph) {
+  float* w = static_cast<float*>(ws);
+  if (exact_k) launch_z<true>(src, sh, s, p, it, n, w, ph);
+  else launch_z<false>(src, sh, s, p, it, n, w, ph);
   return hipGetLastError();
 }
 
@@ -951,9 +1063,12 @@ hipError_t configure_attributes() {
   hipError_t e = hipSuccess, r;
   const void* fns[] = {reinterpret_cast<const void*>(&x_fwd_kernel),
                        reinterpret_cast<const void*>(&x_inv_kernel),
-                       reinterpret_cast<const void*>(&z_fused_kernel<kVacuum>),
-                       reinterpret_cast<const void*>(&z_fused_kernel<kRho>),
-                       reinterpret_cast<const void*>(&z_fused_kernel<kJForm>)};
+                       reinterpret_cast<const void*>(&z_fused_kernel<kVacuum, true>),
+                       reinterpret_cast<const void*>(&z_fused_kernel<kRho, true>),
+                       reinterpret_cast<const void*>(&z_fused_kernel<kJForm, true>),
+                       reinterpret_cast<const void*>(&z_fused_kernel<kVacuum, false>),
+                       reinterpret_cast<const void*>(&z_fused_kernel<kRho, false>),
+                       reinterpret_cast<const void*>(&z_fused_kernel<kJForm, false>)};
   for (const void* f : fns)
     if ((r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim)) != hipSuccess)
       e = r;
@@ -961,7 +1076,9 @@ hipError_t configure_attributes() {
 }
 
 size_t x_lds_bytes() { return sizeof(double) * kRegion * kWaves; }
-size_t z_lds_bytes() { return sizeof(double2) * 2 * kZBuf + sizeof(float) * kNZ; }
+size_t z_lds_bytes() {
+  return sizeof(double2) * 2 * kZBuf + sizeof(float) * kNZ + sizeof(double2) * kZtCount;
+}
 
 }  // namespace fast2d
 }  // namespace psatd

@@ -21,8 +21,9 @@ hipError_t launch_x_fwd(const LaunchShape& sh, hipStream_t s, const PatchDev* p,
                         const WorkItem* it, int n, const FieldPtrs& f, void* ws);
 hipError_t launch_x_inv(const LaunchShape& sh, hipStream_t s, const PatchDev* p,
                         const WorkItem* it, int n, const FieldPtrs& f, void* ws);
-hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t s, const PatchDev* p,
-                          const WorkItem* it, int n, void* ws, Physics ph);
+// exact_k: the plan's k tables hold the exact wavenumbers (order 0).
+hipError_t launch_z_fused(int src, bool exact_k, const LaunchShape& sh, hipStream_t s,
+                          const PatchDev* p, const WorkItem* it, int n, void* ws, Physics ph);
 hipError_t configure_attributes();
 size_t x_lds_bytes();
 size_t z_lds_bytes();

@@ -43,6 +43,9 @@ struct PatchDev {
   int pad0;
   double dt;
   double inv_n;           // 1 / (nx ny nz), folded into the update
+  double dkz;             // 2 pi / (nz dz) when the k tables hold the exact wavenumbers
+                          // (kz of index m is m' dkz, m' = m - nz above nz/2, Nyquist 0);
+                          // 0 when they hold an order-p k_p
   long long off_real;     // element offset in the caller's component buffers
   long long off_spec;     // complex-element offset of this patch's first component
   long long off_z;        // block the z passes work on: off_spec in 2D; in 3D a second

@@ -28,11 +28,12 @@ def _host(t, shape):
     return t.detach().cpu().numpy().astype(np.float64).reshape(shape)
 
 
-def _run(w, steps, generic=False, n0=0, autotune=False):
+def _run(w, steps, generic=False, n0=0, autotune=False, order=0, centered=False):
     import torch
     p = w.patches[0]
     plan = pk.Plan([p], precision="fp32", source_mode="rho", path="fused",
-                   generic_kernels=generic, autotune=autotune)
+                   generic_kernels=generic, autotune=autotune, order=order,
+                   centered_stencil=centered)
     E = [_dev(a) for a in w.E0[0]]
     B = [_dev(a) for a in w.B0[0]]
     for n in range(n0, n0 + steps):
@@ -54,6 +55,24 @@ def test_fullsize_one_step_vs_oracle(w1):
     J, ro, rn = w1.schedule[0].sources(0, dtype=np.float32)
     En, Bn = oracle.psatd_step(E, B, [x.astype(np.float64) for x in J], ro.astype(np.float64),
                                rn.astype(np.float64), d=p.d, dt=p.dt)
+    err = rel_l2(got, En + Bn)
+    say(f"  rel L2 = {err:.3e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("order,centered", [(8, False), (16, True)])
+def test_fullsize_order_p_one_step_vs_oracle(w1, order, centered):
+    # the specialized kernels read kz from the order-p table (exact k: from the index)
+    p = w1.patches[0]
+    say(f"fast path, order {order} {'centered' if centered else 'staggered'}, 1 step vs oracle")
+    got, names = _run(w1, 1, order=order, centered=centered)
+    assert names == ["x_r2c_fwd", "z_fused", "x_c2r_inv"]
+    E = [np.asarray(a, np.float32).astype(np.float64) for a in w1.E0[0]]
+    B = [np.asarray(a, np.float32).astype(np.float64) for a in w1.B0[0]]
+    J, ro, rn = w1.schedule[0].sources(0, dtype=np.float32)
+    En, Bn = oracle.psatd_step(E, B, [x.astype(np.float64) for x in J], ro.astype(np.float64),
+                               rn.astype(np.float64), d=p.d, dt=p.dt, order=order,
+                               stencil="centered" if centered else "staggered")
     err = rel_l2(got, En + Bn)
     say(f"  rel L2 = {err:.3e}")
     assert err < 1e-5
