@@ -516,7 +516,9 @@ Pass make_fast_pass(PassType type, const psatd_plan_s* plan, const std::vector<i
     }
   }
   ps.nitems = static_cast<int>(items.size() - first);
-  const size_t lds = type == kFastZ ? fast2d::z_lds_bytes() : fast2d::x_lds_bytes();
+  const size_t lds = type == kFastZ      ? fast2d::z_lds_bytes()
+                     : type == kFastXFwd ? fast2d::x_fwd_lds_bytes()
+                                         : fast2d::x_inv_lds_bytes();
   // Each kernel fits one workgroup per CU (LDS) and loops over its items when
   // the grid is smaller than the item count.  Default grids as measured at
   // 4096x4096: the z pass walks its columns (prefetching the next one); the x

@@ -30,6 +30,50 @@ constexpr int kRegion = kMX + kMX / 16;  // doubles per wave region (padded)
 
 // Wave regions are padded: logical index i sits at padx(i) = i + (i >> 4).
 
+// After the wave regions, the inverse x pass keeps the per-lane twiddles of
+// every tile in LDS, read from the FP64 tables once per workgroup (a global
+// load inside a tile would hold up the LDS waits that follow it):
+constexpr int kXtB = 0;       // W2048^(8 k), k < 16: stage-B bases (k = l mod 16)
+constexpr int kXtC = 16;      // W2048^m, m < 256: stage-C bases (m = l + 64 b)
+constexpr int kXtPost = 272;  // W4096^m, m <= 512: r2c post-twiddles and their step
+constexpr int kXtCount = 785;
+
+// Element i of a plan table (device memory), read through a global-address-
+// space pointer: a global load, counted by vmcnt only, instead of a flat load,
+// which every LDS wait (lgkmcnt) would also wait for.  (The host pass of the
+// compiler, which never runs this, reads through the plain pointer.)
+template <typename T>
+__device__ __forceinline__ T gload(const T* p, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)p;
+  return g[i];
+#else
+  return p[i];
+#endif
+}
+
+// One twiddle from an LDS table at an index the optimizer cannot see through,
+// so that it is read again where it is used (reuse across tiles or
+// transforms would keep the bases and their powers live through the whole
+// kernel).
+__device__ __forceinline__ double2 lds_twiddle(const double2* t, int idx) {
+  asm volatile("" : "+v"(idx));
+  return t[idx];
+}
+
+// Fill the x-pass table from the plan's FP64 tables (every patch of these
+// passes has nx = 4096 and shares them).
+__device__ __forceinline__ void fill_x_table(double2* xt, const PatchDev* P) {
+  for (int e = threadIdx.x; e < kXtCount; e += blockDim.x) {
+    double2 v;
+    if (e < kXtC) v = P->fx.tw[8 * (e - kXtB)];
+    else if (e < kXtPost) v = P->fx.tw[e - kXtC];
+    else v = P->post[e - kXtPost];
+    xt[e] = v;
+  }
+  __syncthreads();
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
 // XCD b mod 8, and about 256 run at once, one per CU).  Within each run of 256
 // workgroups this gives XCD x the contiguous items [32 x, 32 x + 32), so that
@@ -214,10 +258,10 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
     const int z1 = wi.first;
     const double2* tw2048 = P->fx.tw;
     const double2* tw4096 = P->fz.tw;
-    double2 twB = tw2048[8 * (l & 15)];
+    double2 twB = gload(tw2048, 8 * (l & 15));
     double2 twC[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) twC[b] = tw2048[l + 64 * b];
+    for (int b = 0; b < 4; ++b) twC[b] = gload(tw2048, l + 64 * b);
 
     double2 a[2][16];
 #pragma unroll
@@ -240,9 +284,9 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
     // order, so waiting for a load issued after the prefetch would wait for
     // the whole prefetch.  post[t + 512 i] = post[t] post[512]^i and
     // W4096^(z1 k2) = (W4096^z1)^k2 follow by multiplication.
-    const double2 wk0 = P->post[threadIdx.x];
-    const double2 wstep = P->post[512];
-    const double2 wz1 = tw4096[z1];
+    const double2 wk0 = gload(P->post, static_cast<int>(threadIdx.x));
+    const double2 wstep = gload(P->post, 512);
+    const double2 wz1 = gload(tw4096, z1);
     __builtin_amdgcn_sched_barrier(0);
     // next tile's row (the same workgroup's next item), in flight during the output phase
     const int nit = it + gridDim.x;
@@ -310,11 +354,14 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   double* region = lds_d + w * kRegion;
+  const double2* xt = reinterpret_cast<const double2*>(lds_d + kRegion * kWaves);
+  if (static_cast<int>(blockIdx.x) >= nitems) return;
+  fill_x_table(reinterpret_cast<double2*>(lds_d + kRegion * kWaves),
+               patches + items[xcd_local_order(blockIdx.x, nitems)].patch);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const WorkItem wi = items[xcd_local_order(it, nitems)];
     const PatchDev* P = patches + wi.patch;
     const int z1 = wi.first;
-    const double2* tw2048 = P->fx.tw;
     const float2* in = reinterpret_cast<const float2*>(ws) + P->off_spec +
                        (long long)wi.comp * P->comp_stride;
     // phase 1: inverse DFT over k2 for each kx, into the FP32 staging rows
@@ -346,17 +393,17 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
     }
     __syncthreads();
     // phase 2: wave w owns row z = z1 + 512 w: c2r pre-twiddle, inverse FFT
-    double2 twB = cconj(tw2048[8 * (l & 15)]);
+    double2 twB = cconj(lds_twiddle(xt, kXtB + (l & 15)));
     double2 twC[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) twC[b] = cconj(tw2048[l + 64 * b]);
+    for (int b = 0; b < 4; ++b) twC[b] = cconj(lds_twiddle(xt, kXtC + l + 64 * b));
     const float2* zrow = reinterpret_cast<const float2*>(region);
     const float2* zmir = zrow + (64 - l);
     // pre-twiddles W^k, k = l + 64 b + 128 q: start at W^(l + 64 b), step W^128
     double2 wk[2];
-    wk[0] = P->post[l];
-    wk[1] = P->post[l + 64];
-    const double2 wstep = P->post[128];
+    wk[0] = lds_twiddle(xt, kXtPost + l);
+    wk[1] = lds_twiddle(xt, kXtPost + l + 64);
+    const double2 wstep = lds_twiddle(xt, kXtPost + 128);
     double2 a[2][16];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -426,13 +473,6 @@ constexpr int kZtOut = 72;    // W4096^(jA k2A) of thread tA: first output twidd
 constexpr int kZtStep = 584;  // W4096^(64 k2), k2 < 8: its step over q
 constexpr int kZtCount = 592;
 
-// One twiddle from the LDS table at an index the optimizer cannot see through,
-// so that every transform reads it again (reuse across transforms would keep
-// the bases and their powers live through the whole kernel).
-__device__ __forceinline__ double2 zt_read(const double2* zt, int idx) {
-  asm volatile("" : "+v"(idx));
-  return zt[idx];
-}
 
 template <int SIGN>
 __device__ __forceinline__ void twiddle8(double2 (&v)[8], double2 w) {
@@ -487,7 +527,7 @@ __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = b1[64 * q];
   // stage 2: Ns = 8, k = j mod 8, w = exp(-2 pi i k / 64); outputs 8 (j - k) + k + 8 q
-  twiddle8<-1>(v, zt_read(zt, kZtS2 + (x.jB & 7)));
+  twiddle8<-1>(v, lds_twiddle(zt, kZtS2 + (x.jB & 7)));
   DFT<8, -1>::run(v);
 #pragma unroll
   for (int q = 0; q < 8; ++q) b2[8 * q] = v[q];
@@ -495,7 +535,7 @@ __device__ __forceinline__ void fwd512(double2 (&v)[8], double2* buf, const ZIdx
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = b1[64 * q];
   // stage 3: Ns = 64, k = j, w = exp(-2 pi i j / 512); outputs j + 64 q
-  twiddle8<-1>(v, zt_read(zt, kZtS3 + x.jB));
+  twiddle8<-1>(v, lds_twiddle(zt, kZtS3 + x.jB));
   DFT<8, -1>::run(v);
 }
 
@@ -508,7 +548,7 @@ __device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx
   double2* b2 = buf + x.baseB2;
   // adjoint of stage 3
   DFT<8, 1>::run(v);
-  twiddle8<1>(v, zt_read(zt, kZtS3 + x.jB));  // conjugate twiddles after the butterflies
+  twiddle8<1>(v, lds_twiddle(zt, kZtS3 + x.jB));  // conjugate twiddles after the butterflies
 #pragma unroll
   for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
   wave_lds_sync();
@@ -516,7 +556,7 @@ __device__ __forceinline__ void inv512(double2 (&v)[8], double2* buf, const ZIdx
   for (int q = 0; q < 8; ++q) v[q] = b2[8 * q];
   // adjoint of stage 2
   DFT<8, 1>::run(v);
-  twiddle8<1>(v, zt_read(zt, kZtS2 + (x.jB & 7)));
+  twiddle8<1>(v, lds_twiddle(zt, kZtS2 + (x.jB & 7)));
 #pragma unroll
   for (int q = 0; q < 8; ++q) b1[64 * q] = v[q];
   __syncthreads();
@@ -573,7 +613,7 @@ struct ZCol {
       const int m = idx < kNZ / 2 ? idx : (idx == kNZ / 2 ? 0 : idx - kNZ);
       v = static_cast<double>(m) * dkz;
     } else {
-      v = kzb[x.tB + o];
+      v = gload(kzb, x.tB + o);
     }
     asm volatile("" : "+v"(v));
     return v;
@@ -604,8 +644,8 @@ struct ZCol {
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = ld2(src_b[q]);
     inv512(v, next_buf(), x, zt);
-    double2 tq = cconj(zt_read(zt, kZtOut + x.tA));
-    const double2 step = cconj(zt_read(zt, kZtStep + x.k2A));
+    double2 tq = cconj(lds_twiddle(zt, kZtOut + x.tA));
+    const double2 step = cconj(lds_twiddle(zt, kZtStep + x.k2A));
     float2* dst = col + comp * cs;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1075,7 +1115,8 @@ hipError_t configure_attributes() {
   return e;
 }
 
-size_t x_lds_bytes() { return sizeof(double) * kRegion * kWaves; }
+size_t x_fwd_lds_bytes() { return sizeof(double) * kRegion * kWaves; }
+size_t x_inv_lds_bytes() { return sizeof(double) * kRegion * kWaves + sizeof(double2) * kXtCount; }
 size_t z_lds_bytes() {
   return sizeof(double2) * 2 * kZBuf + sizeof(float) * kNZ + sizeof(double2) * kZtCount;
 }

@@ -25,7 +25,8 @@ hipError_t launch_x_inv(const LaunchShape& sh, hipStream_t s, const PatchDev* p,
 hipError_t launch_z_fused(int src, bool exact_k, const LaunchShape& sh, hipStream_t s,
                           const PatchDev* p, const WorkItem* it, int n, void* ws, Physics ph);
 hipError_t configure_attributes();
-size_t x_lds_bytes();
+size_t x_fwd_lds_bytes();
+size_t x_inv_lds_bytes();
 size_t z_lds_bytes();
 
 }  // namespace fast2d
