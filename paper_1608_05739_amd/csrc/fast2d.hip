@@ -303,6 +303,9 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
     for (int k2 = 2; k2 < 8; ++k2) tz[k2] = cmul(tz[k2 - 1], wz1);
     double2 wk = wk0;
     float2* out = reinterpret_cast<float2*>(ws) + P->off_spec + (long long)wi.comp * P->comp_stride;
+    // The r2c split X = (Z[k] + conj Z[N-k]) / 2 - (i/2) W^k (Z[k] - conj Z[N-k]) is
+    // computed without the halving: this pass delivers 2X, and the z pass
+    // folds the 1/2 into its coefficients (exactly: a power of two).
 #pragma unroll 1
     for (int i = 0; i < 4; ++i) {
       const int kx = threadIdx.x + 512 * i;
@@ -313,11 +316,17 @@ x_fwd_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
         const float2* zr = reinterpret_cast<const float2*>(lds_d + r * kRegion);
         const double2 za = ld_f2(zr + kx);
         const double2 zb = ld_f2(zr + km);  // km = 0 for kx = 0: in bounds, result replaced
-        const double2 e = make_double2(0.5 * (za.x + zb.x), 0.5 * (za.y - zb.y));
-        const double2 d = make_double2(za.x - zb.x, za.y + zb.y);
-        const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);
-        X[r] = cadd(e, cmul(wk, o));
-        if (kx == 0) X[r] = make_double2(za.x + za.y, za.x - za.y);
+        const double2 wd = cmul(wk, make_double2(za.x - zb.x, za.y + zb.y));
+        X[r] = make_double2((za.x + zb.x) + wd.y, (za.y - zb.y) - wd.x);
+      }
+      // kx = 0 holds DC and Nyquist packed (2 Re Z[0] +- 2 Im Z[0]): only the
+      // first thread of the first wave in the first iteration (a uniform branch)
+      if (i == 0 && w == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const double2 za = ld_f2(reinterpret_cast<const float2*>(lds_d + r * kRegion) + kx);
+          if (kx == 0) X[r] = make_double2(2.0 * (za.x + za.y), 2.0 * (za.x - za.y));
+        }
       }
       DFT<8, -1>::run(X);
       float4 ch[4];
@@ -668,7 +677,7 @@ __device__ __forceinline__ ZCol<EXACT> make_zcol(const PatchDev* P, int kxcol, f
   z.c2 = ph.c * ph.c;
   z.eps0 = ph.eps0;
   z.ie = 1.0 / ph.eps0;
-  z.scale = P->inv_n;
+  z.scale = 0.5 * P->inv_n;  // the forward x pass delivers twice the spectrum
   z.dkz = P->dkz;
   z.kzb = P->kz_b;
   z.zt = lds + 2 * kZBuf + kNZ / 4;
