@@ -38,19 +38,6 @@ constexpr int kXtC = 16;      // W2048^m, m < 256: stage-C bases (m = l + 64 b)
 constexpr int kXtPost = 272;  // W4096^m, m <= 512: r2c post-twiddles and their step
 constexpr int kXtCount = 785;
 
-// Element i of a plan table (device memory), read through a global-address-
-// space pointer: a global load, counted by vmcnt only, instead of a flat load,
-// which every LDS wait (lgkmcnt) would also wait for.  (The host pass of the
-// compiler, which never runs this, reads through the plain pointer.)
-template <typename T>
-__device__ __forceinline__ T gload(const T* p, int i) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)p;
-  return g[i];
-#else
-  return p[i];
-#endif
-}
 
 // One twiddle from an LDS table at an index the optimizer cannot see through,
 // so that it is read again where it is used (reuse across tiles or

@@ -33,6 +33,20 @@ __device__ __forceinline__ double2 mul_si(double2 a) {
   else return make_double2(a.y, -a.x);
 }
 
+// Element i of a plan table (device memory), read through a global-address-
+// space pointer: a global load, counted by vmcnt only, instead of a flat load,
+// which every LDS wait (lgkmcnt) would also wait for.  (The host pass of the
+// compiler, which never runs this, reads through the plain pointer.)
+template <typename T>
+__device__ __forceinline__ T gload(const T* p, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)p;
+  return g[i];
+#else
+  return p[i];
+#endif
+}
+
 // ------------------------------------------------------------------ static_for
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -171,13 +185,14 @@ __device__ __forceinline__ void lds_stage(double2* lds, int L, int nl, int LS, i
     if (b < total) {
       const int line = b / nb;
       const int j = b - line * nb;
+      const int k = j % Ns;
+      // the twiddle first (a global load, in flight during the LDS reads)
+      double2 w = gload(tw, k * twstride);
       const double2* src = lds + line * LS + j;
 #pragma unroll
       for (int q = 0; q < R; ++q) v[t][q] = src[q * nb];
-      const int k = j % Ns;
       obase[t] = line * LS + (j - k) * R + k;
       if (k != 0) {
-        double2 w = tw[k * twstride];
         if constexpr (SIGN > 0) w.y = -w.y;
         double2 wq = w;
         v[t][1] = cmul(v[t][1], w);

@@ -90,7 +90,7 @@ __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, co
       const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
       const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
       const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
-      const double2 wo = cmul(post[k], o);
+      const double2 wo = cmul(gload(post, k), o);
       row[k] = cadd(e, wo);
       if (kk != k) row[kk] = cconj(csub(e, wo));
     }
@@ -116,7 +116,7 @@ __device__ __forceinline__ void c2r_pre(double2* lds, int nl, int LS, int M, con
       const double2 b = row[kk];
       const double2 p = make_double2(a.x + b.x, a.y - b.y);
       const double2 m = make_double2(a.x - b.x, a.y + b.y);
-      const double2 w = post[k];
+      const double2 w = gload(post, k);
       const double2 t1 = cmul(cconj(w), m);
       const double2 t2 = cmul(w, cconj(m));
       row[k] = make_double2(p.x - t1.y, p.y + t1.x);
@@ -265,13 +265,13 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
       const int iz = idx % nz;
       double kx, ky;
       if (P->ndim == 2) {
-        kx = P->kx[line];
+        kx = gload(P->kx, static_cast<int>(line));
         ky = 0.0;
       } else {
-        kx = P->kx[line / P->ny];
-        ky = P->ky[line % P->ny];
+        kx = gload(P->kx, static_cast<int>(line / P->ny));
+        ky = gload(P->ky, static_cast<int>(line % P->ny));
       }
-      const double kz = P->kz[iz];
+      const double kz = gload(P->kz, iz);
       double2 E[3] = {}, B[3] = {}, J[3] = {};
       double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
       static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
@@ -361,13 +361,13 @@ update_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__
       const int iz = static_cast<int>(idx - line * nz);
       double kx, ky;
       if (P->ndim == 2) {
-        kx = P->kx[line];
+        kx = gload(P->kx, static_cast<int>(line));
         ky = 0.0;
       } else {
-        kx = P->kx[line / P->ny];
-        ky = P->ky[line % P->ny];
+        kx = gload(P->kx, static_cast<int>(line / P->ny));
+        ky = gload(P->ky, static_cast<int>(line % P->ny));
       }
-      const double kz = P->kz[iz];
+      const double kz = gload(P->kz, iz);
       double2 E[3], B[3], J[3] = {};
       double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
 #pragma unroll
