@@ -358,7 +358,10 @@ int fused_mpt(int precision, int ndim) {
   return ndim == 2 ? 4 : 2;
 }
 
-psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out) {
+// lines_cap > 0 limits the lines (z lines of one patch) per workgroup below
+// what LDS and registers allow (autotuning tries several).
+psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out,
+                             int lines_cap = 0) {
   Pass ps;
   ps.type = kFused;
   ps.name = "z_fused";
@@ -381,8 +384,10 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
     if (P.nz > cap)
       return fail(PSATD_ERR_UNSUPPORTED_SIZE,
                   "fused path: nz = " + std::to_string(P.nz) + " does not fit one workgroup");
-    const int W = std::max(1, std::min(nlines, cap / P.nz));
+    int W = std::max(1, std::min(nlines, cap / P.nz));
+    if (lines_cap > 0) W = std::min(W, lines_cap);
     lds = std::max(lds, static_cast<size_t>(W) * P.nz * sizeof(double2));
+    ps.lines = std::max(ps.lines, W);
     for (int l = 0; l < nlines; l += W)
       items.push_back(WorkItem{static_cast<int>(pi), l, std::min(W, nlines - l), -1});
     const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
@@ -681,10 +686,15 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     };
     std::vector<Cand> cands;
     cands.push_back(Cand{ps, nullptr});
-    if (ps.type == kLine) {
+    if (ps.type == kLine || ps.type == kFused) {
       for (int R : {1, 2, 4, 8, 16, 32}) {
         std::vector<WorkItem> its;
-        Pass c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
+        Pass c;
+        if (ps.type == kLine) {
+          c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
+        } else if (make_fused_pass(plan, its, &c, R) != PSATD_OK) {
+          continue;
+        }
         bool seen = false;
         for (const Cand& x : cands) seen = seen || x.pass.lines == c.lines;
         if (seen) continue;
