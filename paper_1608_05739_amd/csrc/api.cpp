@@ -333,11 +333,12 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
       R = std::max(1, 4096 / L);
     }
     R = std::min(R, nlines);
-    // LDS holds R lines (<= 128 KB) and 512 threads own every stage's points
+    // LDS holds R lines (<= 8192 points, 136 KB padded) and 512 threads own
+    // every stage's points
     const int max_pts = std::min(8192, kLineBlockMax * points_per_thread(L, kMaxPts));
     R = std::max(1, std::min(R, max_pts / L));
     block = std::max(block, threads_for(R * L, L));
-    lds = std::max(lds, static_cast<size_t>(R) * L * sizeof(double2));
+    lds = std::max(lds, static_cast<size_t>(lpad_size(R * L)) * sizeof(double2));
     ps.lines = std::max(ps.lines, R);
     for (int c : comps)
       for (int l = 0; l < nlines; l += R)
@@ -386,7 +387,7 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
                   "fused path: nz = " + std::to_string(P.nz) + " does not fit one workgroup");
     int W = std::max(1, std::min(nlines, cap / P.nz));
     if (lines_cap > 0) W = std::min(W, lines_cap);
-    lds = std::max(lds, static_cast<size_t>(W) * P.nz * sizeof(double2));
+    lds = std::max(lds, static_cast<size_t>(lpad_size(W * P.nz)) * sizeof(double2));
     ps.lines = std::max(ps.lines, W);
     for (int l = 0; l < nlines; l += W)
       items.push_back(WorkItem{static_cast<int>(pi), l, std::min(W, nlines - l), -1});
@@ -470,7 +471,8 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
     if (w.first + w.count > nlines)
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item past the last line");
     const long long pts = static_cast<long long>(w.count) * L;
-    if (pts * static_cast<long long>(sizeof(double2)) > static_cast<long long>(ps.shape.lds_bytes))
+    if (static_cast<long long>(lpad_size(static_cast<int>(pts))) * static_cast<long long>(sizeof(double2)) >
+        static_cast<long long>(ps.shape.lds_bytes))
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item exceeds LDS");
     if (ps.type == kFused && pts > static_cast<long long>(ps.shape.block) * ps.mpt)
       return fail(PSATD_ERR_STATE, "z_fused: modes exceed registers");

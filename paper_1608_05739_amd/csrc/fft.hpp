@@ -162,9 +162,50 @@ struct DFT<16, SIGN> {
   static __device__ __forceinline__ void run(double2* v) { dft_split<4, 4, SIGN>(v); }
 };
 
+// ------------------------------------------------------------------ LDS layout and indices
+// Lines in LDS are padded by one element every 16: logical element i sits at
+// lpad(i) = i + floor(i / 16).  A radix-R stage writes element (j R + q) from
+// lane j; without the padding the lanes of a wave would all hit the same LDS
+// banks when R is 8 or 16.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+
+// Elements of LDS holding n logical elements.
+__host__ __device__ constexpr int lpad_size(int n) { return n + (n >> 4) + 1; }
+
+// q = x / d, r = x mod d for a divisor that every lane shares (a power of two
+// takes a shift and a mask).
+__device__ __forceinline__ void udivmod(int x, int d, int& q, int& r) {
+  if ((d & (d - 1)) == 0) {
+    const int s = __builtin_ctz(d);
+    q = x >> s;
+    r = x & (d - 1);
+  } else {
+    q = x / d;
+    r = x - q * d;
+  }
+}
+
+// Walks idx = threadIdx.x + t blockDim.x as (hi, lo) = (idx / n, idx mod n):
+// one division per thread, then every step adds blockDim.x with a carry.
+struct Walk2 {
+  int hi, lo, dhi, dlo, n;
+  __device__ __forceinline__ explicit Walk2(int n_) : n(n_) {
+    udivmod(static_cast<int>(threadIdx.x), n, hi, lo);
+    udivmod(static_cast<int>(blockDim.x), n, dhi, dlo);
+  }
+  __device__ __forceinline__ void next() {
+    hi += dhi;
+    lo += dlo;
+    if (lo >= n) {
+      lo -= n;
+      ++hi;
+    }
+  }
+};
+
 // ------------------------------------------------------------------ Stockham stage
-// One radix-R stage over nl lines of length L stored in LDS (line stride LS,
-// in place).  Ns is the product of the radices already applied.  Butterfly
+// One radix-R stage over nl lines of length L stored in LDS (line stride LS
+// in logical elements, padded by lpad; in place).  Ns is the product of the radices already applied.  Butterfly
 // j of a line reads x[j + q L/R], multiplies by w^q with
 // w = exp(SIGN 2 pi i (j mod Ns) / (Ns R)), applies DFT<R> and writes
 // y[(j - j mod Ns) R + j mod Ns + q Ns].  Each thread handles at most
@@ -174,44 +215,47 @@ __device__ __forceinline__ void lds_stage(double2* lds, int L, int nl, int LS, i
                                           const double2* __restrict__ tw) {
   constexpr int BPT = MAXPTS / R;
   const int nb = L / R;
-  const int total = nb * nl;
-  const int T = blockDim.x;
   const int twstride = L / (Ns * R);
+  // butterfly b = threadIdx.x + t blockDim.x is index j of line `line`, and
+  // k = j mod Ns; Ns divides nb, so a carry out of j leaves k unchanged
+  Walk2 w(nb);
+  int k, dk, unused;
+  udivmod(w.lo, Ns, unused, k);
+  udivmod(w.dlo, Ns, unused, dk);
   double2 v[BPT][R];
   int obase[BPT];
 #pragma unroll
   for (int t = 0; t < BPT; ++t) {
-    const int b = threadIdx.x + t * T;
-    if (b < total) {
-      const int line = b / nb;
-      const int j = b - line * nb;
-      const int k = j % Ns;
+    obase[t] = -1;
+    if (w.hi < nl) {
       // the twiddle first (a global load, in flight during the LDS reads)
-      double2 w = gload(tw, k * twstride);
-      const double2* src = lds + line * LS + j;
+      double2 wt = gload(tw, k * twstride);
+      const int src = w.hi * LS + w.lo;
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[t][q] = src[q * nb];
-      obase[t] = line * LS + (j - k) * R + k;
+      for (int q = 0; q < R; ++q) v[t][q] = lds[lpad(src + q * nb)];
+      obase[t] = w.hi * LS + (w.lo - k) * R + k;
       if (k != 0) {
-        if constexpr (SIGN > 0) w.y = -w.y;
-        double2 wq = w;
-        v[t][1] = cmul(v[t][1], w);
+        if constexpr (SIGN > 0) wt.y = -wt.y;
+        double2 wq = wt;
+        v[t][1] = cmul(v[t][1], wt);
 #pragma unroll
         for (int q = 2; q < R; ++q) {
-          wq = cmul(wq, w);
+          wq = cmul(wq, wt);
           v[t][q] = cmul(v[t][q], wq);
         }
       }
     }
+    w.next();
+    k += dk;
+    if (k >= Ns) k -= Ns;
   }
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < BPT; ++t) {
-    const int b = threadIdx.x + t * T;
-    if (b < total) {
+    if (obase[t] >= 0) {
       DFT<R, SIGN>::run(v[t]);
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[obase[t] + q * Ns] = v[t][q];
+      for (int q = 0; q < R; ++q) lds[lpad(obase[t] + q * Ns)] = v[t][q];
     }
   }
   __syncthreads();

@@ -62,10 +62,17 @@ __device__ __forceinline__ TileMap tile_map(int kind, const PatchDev* P) {
   return t;
 }
 
+// Element n of line l in the tile layout: (l mod A) + (l / A) B + n C.
+__device__ __forceinline__ long long tile_offset(const TileMap& t, int l, int n) {
+  int q, r;
+  udivmod(l, static_cast<int>(t.A), q, r);
+  return r + q * t.B + n * t.C;
+}
+
 // Start of contiguous line l for the y passes ([z][kx][y]: l = kx*nz + z).
 __device__ __forceinline__ long long yline_start(const PatchDev* P, int l) {
-  const int z = l % P->nz;
-  const int kx = l / P->nz;
+  int kx, z;
+  udivmod(l, P->nz, kx, z);
   return ((long long)z * P->mx + kx) * P->ny;
 }
 
@@ -76,23 +83,23 @@ __device__ __forceinline__ long long yline_start(const PatchDev* P, int l) {
 // Column 0 is packed as F[0] + i F[M] (both real).
 __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
   const int npair = M / 2 + 1;
-  for (int idx = threadIdx.x; idx < nl * npair; idx += blockDim.x) {
-    const int r = idx / npair;
-    const int k = idx - r * npair;
-    double2* row = lds + r * LS;
+  for (Walk2 w(npair); w.hi < nl; w.next()) {
+    const int r = w.hi;
+    const int k = w.lo;
+    const int row = r * LS;
     if (k == 0) {
-      const double2 z = row[0];
-      row[0] = make_double2(z.x + z.y, z.x - z.y);
+      const double2 z = lds[lpad(row)];
+      lds[lpad(row)] = make_double2(z.x + z.y, z.x - z.y);
     } else {
       const int kk = M - k;
-      const double2 a = row[k];
-      const double2 b = row[kk];
+      const double2 a = lds[lpad(row + k)];
+      const double2 b = lds[lpad(row + kk)];
       const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
       const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
       const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
       const double2 wo = cmul(gload(post, k), o);
-      row[k] = cadd(e, wo);
-      if (kk != k) row[kk] = cconj(csub(e, wo));
+      lds[lpad(row + k)] = cadd(e, wo);
+      if (kk != k) lds[lpad(row + kk)] = cconj(csub(e, wo));
     }
   }
   __syncthreads();
@@ -103,24 +110,24 @@ __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, co
 // column 0: Z'[0] = (F0 + FM) + i (F0 - FM).
 __device__ __forceinline__ void c2r_pre(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
   const int npair = M / 2 + 1;
-  for (int idx = threadIdx.x; idx < nl * npair; idx += blockDim.x) {
-    const int r = idx / npair;
-    const int k = idx - r * npair;
-    double2* row = lds + r * LS;
+  for (Walk2 w(npair); w.hi < nl; w.next()) {
+    const int r = w.hi;
+    const int k = w.lo;
+    const int row = r * LS;
     if (k == 0) {
-      const double2 x = row[0];
-      row[0] = make_double2(x.x + x.y, x.x - x.y);
+      const double2 x = lds[lpad(row)];
+      lds[lpad(row)] = make_double2(x.x + x.y, x.x - x.y);
     } else {
       const int kk = M - k;
-      const double2 a = row[k];
-      const double2 b = row[kk];
+      const double2 a = lds[lpad(row + k)];
+      const double2 b = lds[lpad(row + kk)];
       const double2 p = make_double2(a.x + b.x, a.y - b.y);
       const double2 m = make_double2(a.x - b.x, a.y + b.y);
       const double2 w = gload(post, k);
       const double2 t1 = cmul(cconj(w), m);
       const double2 t2 = cmul(w, cconj(m));
-      row[k] = make_double2(p.x - t1.y, p.y + t1.x);
-      if (kk != k) row[kk] = make_double2(p.x - t2.y, -p.y + t2.x);
+      lds[lpad(row + k)] = make_double2(p.x - t1.y, p.y + t1.x);
+      if (kk != k) lds[lpad(row + kk)] = make_double2(p.x - t2.y, -p.y + t2.x);
     }
   }
   __syncthreads();
@@ -157,28 +164,20 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
     if constexpr (KIND == kXFwd) {
       const V* src = reinterpret_cast<const V*>(static_cast<const S*>(fields.f[wi.comp]) +
                                                 P->off_real);
-      for (int idx = threadIdx.x; idx < total; idx += T) {
-        const int r = idx / L;
-        const int n = idx - r * L;
-        lds[r * LS + n] = to_d2(src[(long long)(l0 + r) * L + n]);
-      }
+      for (Walk2 w(L); w.hi < nl; w.next())
+        lds[lpad(w.hi * LS + w.lo)] = to_d2(src[(long long)(l0 + w.hi) * L + w.lo]);
     } else if constexpr (KIND == kXInv || KIND == kYInv) {
       const TileMap tm = tile_map(KIND, P);
-      for (int idx = threadIdx.x; idx < total; idx += T) {
-        const int n = idx / nl;
-        const int r = idx - n * nl;
-        const long long l = l0 + r;
-        lds[r * LS + n] = to_d2(spec[(l % tm.A) + (l / tm.A) * tm.B + n * tm.C]);
+      for (Walk2 w(nl); w.hi < L; w.next()) {
+        const int n = w.hi, r = w.lo;
+        lds[lpad(r * LS + n)] = to_d2(spec[tile_offset(tm, l0 + r, n)]);
       }
     } else if constexpr (KIND == kYFwd) {
-      for (int idx = threadIdx.x; idx < total; idx += T) {
-        const int r = idx / L;
-        const int n = idx - r * L;
-        lds[r * LS + n] = to_d2(spec[yline_start(P, l0 + r) + n]);
-      }
+      for (Walk2 w(L); w.hi < nl; w.next())
+        lds[lpad(w.hi * LS + w.lo)] = to_d2(spec[yline_start(P, l0 + w.hi) + w.lo]);
     } else {  // z lines, contiguous
       const V* src = spec + (long long)l0 * L;
-      for (int idx = threadIdx.x; idx < total; idx += T) lds[idx] = to_d2(src[idx]);
+      for (int idx = threadIdx.x; idx < total; idx += T) lds[lpad(idx)] = to_d2(src[idx]);
     }
     __syncthreads();
 
@@ -189,28 +188,20 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
     // ---------------- store
     if constexpr (KIND == kXFwd || KIND == kYFwd) {
       const TileMap tm = tile_map(KIND, P);
-      for (int idx = threadIdx.x; idx < total; idx += T) {
-        const int n = idx / nl;
-        const int r = idx - n * nl;
-        const long long l = l0 + r;
-        spec_out[(l % tm.A) + (l / tm.A) * tm.B + n * tm.C] = from_d2<V>(lds[r * LS + n]);
+      for (Walk2 w(nl); w.hi < L; w.next()) {
+        const int n = w.hi, r = w.lo;
+        spec_out[tile_offset(tm, l0 + r, n)] = from_d2<V>(lds[lpad(r * LS + n)]);
       }
     } else if constexpr (KIND == kXInv) {
       V* dst = reinterpret_cast<V*>(static_cast<S*>(fields.f[wi.comp]) + P->off_real);
-      for (int idx = threadIdx.x; idx < total; idx += T) {
-        const int r = idx / L;
-        const int n = idx - r * L;
-        dst[(long long)(l0 + r) * L + n] = from_d2<V>(lds[r * LS + n]);
-      }
+      for (Walk2 w(L); w.hi < nl; w.next())
+        dst[(long long)(l0 + w.hi) * L + w.lo] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);
     } else if constexpr (KIND == kYInv) {
-      for (int idx = threadIdx.x; idx < total; idx += T) {
-        const int r = idx / L;
-        const int n = idx - r * L;
-        spec_out[yline_start(P, l0 + r) + n] = from_d2<V>(lds[r * LS + n]);
-      }
+      for (Walk2 w(L); w.hi < nl; w.next())
+        spec_out[yline_start(P, l0 + w.hi) + w.lo] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);
     } else {
       V* dst = spec_out + (long long)l0 * L;
-      for (int idx = threadIdx.x; idx < total; idx += T) dst[idx] = from_d2<V>(lds[idx]);
+      for (int idx = threadIdx.x; idx < total; idx += T) dst[idx] = from_d2<V>(lds[lpad(idx)]);
     }
     __syncthreads();
   }
@@ -239,7 +230,7 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
 #pragma nounroll
   for (int slot = 0; slot < NIN; ++slot) {
     const V* src = base + Gr::in[slot] * cs;
-    for (int idx = threadIdx.x; idx < nmodes; idx += T) lds[idx] = to_d2(src[idx]);
+    for (int idx = threadIdx.x; idx < nmodes; idx += T) lds[lpad(idx)] = to_d2(src[idx]);
     __syncthreads();
     fft_lds<-1, kMaxPtsFused>(lds, W, nz, F);
     static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
@@ -248,7 +239,7 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
 #pragma unroll
         for (int m = 0; m < MPT; ++m) {
           const int idx = threadIdx.x + m * T;
-          if (idx < nmodes) reg[sl][m] = from_d2<V>(lds[idx]);
+          if (idx < nmodes) reg[sl][m] = from_d2<V>(lds[lpad(idx)]);
         }
       }
     });
@@ -261,15 +252,18 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
   for (int m = 0; m < MPT; ++m) {
     const int idx = threadIdx.x + m * T;
     if (idx < nmodes) {
-      const int line = wi.first + idx / nz;
-      const int iz = idx % nz;
+      int lrel, iz;
+      udivmod(idx, nz, lrel, iz);
+      const int line = wi.first + lrel;
       double kx, ky;
       if (P->ndim == 2) {
-        kx = gload(P->kx, static_cast<int>(line));
+        kx = gload(P->kx, line);
         ky = 0.0;
       } else {
-        kx = gload(P->kx, static_cast<int>(line / P->ny));
-        ky = gload(P->ky, static_cast<int>(line % P->ny));
+        int ix, iy;
+        udivmod(line, P->ny, ix, iy);
+        kx = gload(P->kx, ix);
+        ky = gload(P->ky, iy);
       }
       const double kz = gload(P->kz, iz);
       double2 E[3] = {}, B[3] = {}, J[3] = {};
@@ -313,14 +307,14 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
 #pragma unroll
         for (int m = 0; m < MPT; ++m) {
           const int idx = threadIdx.x + m * T;
-          if (idx < nmodes) lds[idx] = to_d2(reg[sl][m]);
+          if (idx < nmodes) lds[lpad(idx)] = to_d2(reg[sl][m]);
         }
       }
     });
     __syncthreads();
     fft_lds<1, kMaxPtsFused>(lds, W, nz, F);
     V* dst = base + Gr::in[slot] * cs;
-    for (int idx = threadIdx.x; idx < nmodes; idx += T) dst[idx] = from_d2<V>(lds[idx]);
+    for (int idx = threadIdx.x; idx < nmodes; idx += T) dst[idx] = from_d2<V>(lds[lpad(idx)]);
     __syncthreads();
   }
 }
