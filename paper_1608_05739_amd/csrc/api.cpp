@@ -474,6 +474,8 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
     if (static_cast<long long>(lpad_size(static_cast<int>(pts))) * static_cast<long long>(sizeof(double2)) >
         static_cast<long long>(ps.shape.lds_bytes))
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item exceeds LDS");
+    if (ps.type == kLine && pts > static_cast<long long>(ps.shape.block) * kMaxPts)
+      return fail(PSATD_ERR_STATE, std::string(ps.name) + ": tile exceeds the loads a thread holds");
     if (ps.type == kFused && pts > static_cast<long long>(ps.shape.block) * ps.mpt)
       return fail(PSATD_ERR_STATE, "z_fused: modes exceed registers");
     for (int s = 0; s < f->nstages; ++s) {

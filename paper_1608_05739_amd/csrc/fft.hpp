@@ -222,32 +222,47 @@ __device__ __forceinline__ void lds_stage(double2* lds, int L, int nl, int LS, i
   int k, dk, unused;
   udivmod(w.lo, Ns, unused, k);
   udivmod(w.dlo, Ns, unused, dk);
+  // Twiddles first, for every butterfly slot (k < Ns keeps the index inside
+  // the table even for slots past the tile), so that they are in flight
+  // during the LDS reads; k = 0 takes tw[0] = 1, which multiplies exactly.
+  double2 wt[BPT];
+  {
+    int kk = k;
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+      wt[t] = gload(tw, kk * twstride);
+      kk += dk;
+      if (kk >= Ns) kk -= Ns;
+    }
+  }
   double2 v[BPT][R];
   int obase[BPT];
 #pragma unroll
   for (int t = 0; t < BPT; ++t) {
     obase[t] = -1;
     if (w.hi < nl) {
-      // the twiddle first (a global load, in flight during the LDS reads)
-      double2 wt = gload(tw, k * twstride);
       const int src = w.hi * LS + w.lo;
 #pragma unroll
       for (int q = 0; q < R; ++q) v[t][q] = lds[lpad(src + q * nb)];
       obase[t] = w.hi * LS + (w.lo - k) * R + k;
-      if (k != 0) {
-        if constexpr (SIGN > 0) wt.y = -wt.y;
-        double2 wq = wt;
-        v[t][1] = cmul(v[t][1], wt);
-#pragma unroll
-        for (int q = 2; q < R; ++q) {
-          wq = cmul(wq, wt);
-          v[t][q] = cmul(v[t][q], wq);
-        }
-      }
     }
     w.next();
     k += dk;
     if (k >= Ns) k -= Ns;
+  }
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    if (obase[t] >= 0) {
+      double2 u = wt[t];
+      if constexpr (SIGN > 0) u.y = -u.y;
+      double2 uq = u;
+      v[t][1] = cmul(v[t][1], u);
+#pragma unroll
+      for (int q = 2; q < R; ++q) {
+        uq = cmul(uq, u);
+        v[t][q] = cmul(v[t][q], uq);
+      }
+    }
   }
   __syncthreads();
 #pragma unroll

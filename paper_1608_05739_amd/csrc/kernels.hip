@@ -81,25 +81,45 @@ __device__ __forceinline__ long long yline_start(const PatchDev* P, int l) {
 //   F[k] = E[k] + W^k O[k],  E = (Z[k] + conj Z[M-k])/2,  O = -i (Z[k] - conj Z[M-k])/2,
 //   F[M-k] = conj(E[k] - W^k O[k]),  W = exp(-2 pi i / (2M)).
 // Column 0 is packed as F[0] + i F[M] (both real).
+// The pairs (k, M-k) of a thread are taken in groups of kPairGroup: the post
+// twiddles of a group are requested before its LDS work, so their loads are in
+// flight together.  Distinct pairs touch distinct elements.
+constexpr int kPairGroup = 4;
+
 __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
   const int npair = M / 2 + 1;
-  for (Walk2 w(npair); w.hi < nl; w.next()) {
-    const int r = w.hi;
-    const int k = w.lo;
-    const int row = r * LS;
-    if (k == 0) {
-      const double2 z = lds[lpad(row)];
-      lds[lpad(row)] = make_double2(z.x + z.y, z.x - z.y);
-    } else {
-      const int kk = M - k;
-      const double2 a = lds[lpad(row + k)];
-      const double2 b = lds[lpad(row + kk)];
-      const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-      const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
-      const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
-      const double2 wo = cmul(gload(post, k), o);
-      lds[lpad(row + k)] = cadd(e, wo);
-      if (kk != k) lds[lpad(row + kk)] = cconj(csub(e, wo));
+  Walk2 w(npair);
+  while (w.hi < nl) {
+    int row[kPairGroup], kk[kPairGroup];
+    double2 wk[kPairGroup];
+#pragma unroll
+    for (int g = 0; g < kPairGroup; ++g) {
+      row[g] = -1;
+      if (w.hi < nl) {
+        row[g] = w.hi * LS;
+        kk[g] = w.lo;
+        wk[g] = gload(post, w.lo);
+      }
+      w.next();
+    }
+#pragma unroll
+    for (int g = 0; g < kPairGroup; ++g) {
+      if (row[g] < 0) continue;
+      const int k = kk[g];
+      if (k == 0) {
+        const double2 z = lds[lpad(row[g])];
+        lds[lpad(row[g])] = make_double2(z.x + z.y, z.x - z.y);
+      } else {
+        const int km = M - k;
+        const double2 a = lds[lpad(row[g] + k)];
+        const double2 b = lds[lpad(row[g] + km)];
+        const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
+        const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
+        const double2 wo = cmul(wk[g], o);
+        lds[lpad(row[g] + k)] = cadd(e, wo);
+        if (km != k) lds[lpad(row[g] + km)] = cconj(csub(e, wo));
+      }
     }
   }
   __syncthreads();
@@ -110,24 +130,38 @@ __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, co
 // column 0: Z'[0] = (F0 + FM) + i (F0 - FM).
 __device__ __forceinline__ void c2r_pre(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
   const int npair = M / 2 + 1;
-  for (Walk2 w(npair); w.hi < nl; w.next()) {
-    const int r = w.hi;
-    const int k = w.lo;
-    const int row = r * LS;
-    if (k == 0) {
-      const double2 x = lds[lpad(row)];
-      lds[lpad(row)] = make_double2(x.x + x.y, x.x - x.y);
-    } else {
-      const int kk = M - k;
-      const double2 a = lds[lpad(row + k)];
-      const double2 b = lds[lpad(row + kk)];
-      const double2 p = make_double2(a.x + b.x, a.y - b.y);
-      const double2 m = make_double2(a.x - b.x, a.y + b.y);
-      const double2 w = gload(post, k);
-      const double2 t1 = cmul(cconj(w), m);
-      const double2 t2 = cmul(w, cconj(m));
-      lds[lpad(row + k)] = make_double2(p.x - t1.y, p.y + t1.x);
-      if (kk != k) lds[lpad(row + kk)] = make_double2(p.x - t2.y, -p.y + t2.x);
+  Walk2 w(npair);
+  while (w.hi < nl) {
+    int row[kPairGroup], kk[kPairGroup];
+    double2 wk[kPairGroup];
+#pragma unroll
+    for (int g = 0; g < kPairGroup; ++g) {
+      row[g] = -1;
+      if (w.hi < nl) {
+        row[g] = w.hi * LS;
+        kk[g] = w.lo;
+        wk[g] = gload(post, w.lo);
+      }
+      w.next();
+    }
+#pragma unroll
+    for (int g = 0; g < kPairGroup; ++g) {
+      if (row[g] < 0) continue;
+      const int k = kk[g];
+      if (k == 0) {
+        const double2 x = lds[lpad(row[g])];
+        lds[lpad(row[g])] = make_double2(x.x + x.y, x.x - x.y);
+      } else {
+        const int km = M - k;
+        const double2 a = lds[lpad(row[g] + k)];
+        const double2 b = lds[lpad(row[g] + km)];
+        const double2 p = make_double2(a.x + b.x, a.y - b.y);
+        const double2 m = make_double2(a.x - b.x, a.y + b.y);
+        const double2 t1 = cmul(cconj(wk[g]), m);
+        const double2 t2 = cmul(wk[g], cconj(m));
+        lds[lpad(row[g] + k)] = make_double2(p.x - t1.y, p.y + t1.x);
+        if (km != k) lds[lpad(row[g] + km)] = make_double2(p.x - t2.y, -p.y + t2.x);
+      }
     }
   }
   __syncthreads();
@@ -161,23 +195,53 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
     V* spec_out = (KIND == kXFwd || KIND == kXInv || KIND == kYInv) ? blk_x : blk_z;  // stores
 
     // ---------------- load
-    if constexpr (KIND == kXFwd) {
-      const V* src = reinterpret_cast<const V*>(static_cast<const S*>(fields.f[wi.comp]) +
-                                                P->off_real);
-      for (Walk2 w(L); w.hi < nl; w.next())
-        lds[lpad(w.hi * LS + w.lo)] = to_d2(src[(long long)(l0 + w.hi) * L + w.lo]);
-    } else if constexpr (KIND == kXInv || KIND == kYInv) {
+    // Every element a thread owns (at most kMaxPts) is requested before the
+    // first one is written to LDS, so a thread's loads are in flight together.
+    V r[kMaxPts];
+    if constexpr (KIND == kXInv || KIND == kYInv) {
+      // strided side: element n of tile line r goes to LDS element r LS + n
       const TileMap tm = tile_map(KIND, P);
-      for (Walk2 w(nl); w.hi < L; w.next()) {
-        const int n = w.hi, r = w.lo;
-        lds[lpad(r * LS + n)] = to_d2(spec[tile_offset(tm, l0 + r, n)]);
+      int dst[kMaxPts];
+      Walk2 w(nl);
+#pragma unroll
+      for (int t = 0; t < kMaxPts; ++t) {
+        dst[t] = -1;
+        if (w.hi < L) {
+          r[t] = spec[tile_offset(tm, l0 + w.lo, w.hi)];
+          dst[t] = w.lo * LS + w.hi;
+        }
+        w.next();
       }
-    } else if constexpr (KIND == kYFwd) {
-      for (Walk2 w(L); w.hi < nl; w.next())
-        lds[lpad(w.hi * LS + w.lo)] = to_d2(spec[yline_start(P, l0 + w.hi) + w.lo]);
-    } else {  // z lines, contiguous
-      const V* src = spec + (long long)l0 * L;
-      for (int idx = threadIdx.x; idx < total; idx += T) lds[lpad(idx)] = to_d2(src[idx]);
+#pragma unroll
+      for (int t = 0; t < kMaxPts; ++t)
+        if (dst[t] >= 0) lds[lpad(dst[t])] = to_d2(r[t]);
+    } else {
+      // lines of the tile in LDS order: element idx = (line, n) sits at idx
+      if constexpr (KIND == kYFwd) {
+        Walk2 w(L);
+#pragma unroll
+        for (int t = 0; t < kMaxPts; ++t) {
+          if (w.hi < nl) r[t] = spec[yline_start(P, l0 + w.hi) + w.lo];
+          w.next();
+        }
+      } else {
+        // x rows (real pairs) or z lines: the tile is contiguous
+        const V* src = KIND == kXFwd
+                           ? reinterpret_cast<const V*>(static_cast<const S*>(fields.f[wi.comp]) +
+                                                        P->off_real)
+                           : spec;
+        src += (long long)l0 * L;
+#pragma unroll
+        for (int t = 0; t < kMaxPts; ++t) {
+          const int idx = threadIdx.x + t * T;
+          if (idx < total) r[t] = src[idx];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kMaxPts; ++t) {
+        const int idx = threadIdx.x + t * T;
+        if (idx < total) lds[lpad(idx)] = to_d2(r[t]);
+      }
     }
     __syncthreads();
 
@@ -230,7 +294,23 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
 #pragma nounroll
   for (int slot = 0; slot < NIN; ++slot) {
     const V* src = base + Gr::in[slot] * cs;
-    for (int idx = threadIdx.x; idx < nmodes; idx += T) lds[lpad(idx)] = to_d2(src[idx]);
+    // a thread's loads go out in groups of PF, each group in flight together
+    // before its LDS writes (the group is small: reg holds the other slots)
+    constexpr int PF = MPT < 4 ? MPT : 4;
+#pragma unroll
+    for (int m0 = 0; m0 < MPT; m0 += PF) {
+      V pf[PF];
+#pragma unroll
+      for (int m = 0; m < PF; ++m) {
+        const int idx = threadIdx.x + (m0 + m) * T;
+        if (idx < nmodes) pf[m] = src[idx];
+      }
+#pragma unroll
+      for (int m = 0; m < PF; ++m) {
+        const int idx = threadIdx.x + (m0 + m) * T;
+        if (idx < nmodes) lds[lpad(idx)] = to_d2(pf[m]);
+      }
+    }
     __syncthreads();
     fft_lds<-1, kMaxPtsFused>(lds, W, nz, F);
     static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
