@@ -61,19 +61,6 @@ __device__ __forceinline__ void fill_x_table(double2* xt, const PatchDev* P) {
   __syncthreads();
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
-// XCD b mod 8, and about 256 run at once, one per CU).  Within each run of 256
-// workgroups this gives XCD x the contiguous items [32 x, 32 x + 32), so that
-// neighbouring tiles, which share 128-byte lines of the [kx][8 z1 + k2]
-// spectra, meet in the same L2.  A bijection on [0, n); the tail past the
-// last full run of 256 keeps its order.
-__device__ __forceinline__ int xcd_local_order(int b, int n) {
-  const int base = b & ~255;
-  if (base + 256 > n) return b;
-  const int r = b & 255;
-  return base + (r & 7) * 32 + (r >> 3);
-}
-
 // Order LDS traffic within one wavefront (no other wave touches the region).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -73,6 +73,20 @@ struct WorkItem {
   int comp;
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b mod 8, and about 256 run at once, one per CU).  Within each run of 256
+// workgroups this gives XCD x the contiguous items [32 x, 32 x + 32), so that
+// neighbouring tiles, which share 128-byte lines of the [kx][8 z1 + k2]
+// spectra (or, in the generic line passes, the 64-byte halves of one line of a
+// tile's strided side), meet in the same L2.  A bijection on [0, n); the tail
+// past the last full run of 256 keeps its order.
+__device__ __forceinline__ int xcd_local_order(int b, int n) {
+  const int base = b & ~255;
+  if (base + 256 > n) return b;
+  const int r = b & 255;
+  return base + (r & 7) * 32 + (r >> 3);
+}
+
 // Caller field pointers (real arrays), indexed by Comp.
 struct FieldPtrs {
   void* f[kMaxComp];

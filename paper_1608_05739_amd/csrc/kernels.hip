@@ -177,7 +177,7 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
   constexpr int SIGN = (KIND == kXFwd || KIND == kYFwd || KIND == kZFwd) ? -1 : 1;
   const int T = blockDim.x;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const WorkItem wi = items[it];
+    const WorkItem wi = items[xcd_local_order(it, nitems)];
     const PatchDev* P = patches + wi.patch;
     const FFTPlanDev* F = (KIND == kXFwd || KIND == kXInv)   ? &P->fx
                           : (KIND == kYFwd || KIND == kYInv) ? &P->fy
