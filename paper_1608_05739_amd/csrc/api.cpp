@@ -369,6 +369,7 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
   ps.mpt = fused_mpt(plan->cfg.precision, plan->ndim);
   const int block = kFusedBlock;
   const int modes = block * ps.mpt;
+  const int sl = fused_slots(ps.mpt);
   const size_t first = items.size();
   size_t lds = 0;
   double bytes = 0.0;
@@ -379,15 +380,16 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
       return fail(PSATD_ERR_UNSUPPORTED_SIZE,
                   "fused path: nz = " + std::to_string(P.nz) + " exceeds " + std::to_string(modes) +
                       " modes per workgroup at this precision; use PSATD_PATH_PLAIN");
-    // lines per workgroup: all modes must fit T * MPT, and every FFT stage must
-    // leave at most kMaxPtsFused points per thread
-    const int cap = std::min(modes, block * points_per_thread(P.nz, kMaxPtsFused));
+    // lines per workgroup: all modes must fit T * MPT, and every FFT stage over
+    // the fused_slots(mpt) tiles transformed together must leave at most
+    // kMaxPtsFused points per thread
+    const int cap = std::min(modes, block * points_per_thread(P.nz, kMaxPtsFused) / sl);
     if (P.nz > cap)
       return fail(PSATD_ERR_UNSUPPORTED_SIZE,
                   "fused path: nz = " + std::to_string(P.nz) + " does not fit one workgroup");
     int W = std::max(1, std::min(nlines, cap / P.nz));
     if (lines_cap > 0) W = std::min(W, lines_cap);
-    lds = std::max(lds, static_cast<size_t>(lpad_size(W * P.nz)) * sizeof(double2));
+    lds = std::max(lds, static_cast<size_t>(lpad_size(sl * W * P.nz)) * sizeof(double2));
     ps.lines = std::max(ps.lines, W);
     for (int l = 0; l < nlines; l += W)
       items.push_back(WorkItem{static_cast<int>(pi), l, std::min(W, nlines - l), -1});
@@ -470,13 +472,16 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
     }
     if (w.first + w.count > nlines)
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item past the last line");
-    const long long pts = static_cast<long long>(w.count) * L;
+    // points of one FFT: a fused pass transforms fused_slots tiles together
+    const long long pts =
+        static_cast<long long>(w.count) * L * (ps.type == kFused ? fused_slots(ps.mpt) : 1);
     if (static_cast<long long>(lpad_size(static_cast<int>(pts))) * static_cast<long long>(sizeof(double2)) >
         static_cast<long long>(ps.shape.lds_bytes))
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item exceeds LDS");
     if (ps.type == kLine && pts > static_cast<long long>(ps.shape.block) * kMaxPts)
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": tile exceeds the loads a thread holds");
-    if (ps.type == kFused && pts > static_cast<long long>(ps.shape.block) * ps.mpt)
+    if (ps.type == kFused &&
+        static_cast<long long>(w.count) * L > static_cast<long long>(ps.shape.block) * ps.mpt)
       return fail(PSATD_ERR_STATE, "z_fused: modes exceed registers");
     for (int s = 0; s < f->nstages; ++s) {
       const int r = f->radix[s];

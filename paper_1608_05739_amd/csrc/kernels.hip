@@ -287,39 +287,49 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
   const long long cs = P->comp_stride;
   const FFTPlanDev* F = &P->fz;
 
+  // SL slots are transformed together: their tiles sit one after another in
+  // LDS and one FFT covers all of them, so that the stages have work for
+  // every thread (SL W nz <= T kMaxPtsFused) and share their barriers.
+  constexpr int SL = fused_slots(MPT);
   V reg[NIN][MPT];
-  // Forward transforms of the group's inputs.  The slot loop is a runtime loop
-  // so that the FFT code is instantiated once; the register slot is then
+  // Forward transforms of the group's inputs.  The round loop is a runtime
+  // loop so that the FFT code is instantiated once; the register slot is then
   // selected by a compile-time compare chain (no dynamic register indexing).
 #pragma nounroll
-  for (int slot = 0; slot < NIN; ++slot) {
-    const V* src = base + Gr::in[slot] * cs;
-    // a thread's loads go out in groups of PF, each group in flight together
-    // before its LDS writes (the group is small: reg holds the other slots)
-    constexpr int PF = MPT < 4 ? MPT : 4;
+  for (int s0 = 0; s0 < NIN; s0 += SL) {
+    const int ns = NIN - s0 < SL ? NIN - s0 : SL;
 #pragma unroll
-    for (int m0 = 0; m0 < MPT; m0 += PF) {
-      V pf[PF];
+    for (int j = 0; j < SL; ++j) {
+      if (j >= ns) break;
+      const V* src = base + Gr::in[s0 + j] * cs;
+      // a thread's loads go out in groups of PF, each group in flight
+      // together before its LDS writes (small: reg holds the other slots)
+      constexpr int PF = MPT < 4 ? MPT : 4;
 #pragma unroll
-      for (int m = 0; m < PF; ++m) {
-        const int idx = threadIdx.x + (m0 + m) * T;
-        if (idx < nmodes) pf[m] = src[idx];
-      }
+      for (int m0 = 0; m0 < MPT; m0 += PF) {
+        V pf[PF];
 #pragma unroll
-      for (int m = 0; m < PF; ++m) {
-        const int idx = threadIdx.x + (m0 + m) * T;
-        if (idx < nmodes) lds[lpad(idx)] = to_d2(pf[m]);
+        for (int m = 0; m < PF; ++m) {
+          const int idx = threadIdx.x + (m0 + m) * T;
+          if (idx < nmodes) pf[m] = src[idx];
+        }
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+          const int idx = threadIdx.x + (m0 + m) * T;
+          if (idx < nmodes) lds[lpad(j * nmodes + idx)] = to_d2(pf[m]);
+        }
       }
     }
     __syncthreads();
-    fft_lds<-1, kMaxPtsFused>(lds, W, nz, F);
+    fft_lds<-1, kMaxPtsFused>(lds, ns * W, nz, F);
     static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
       constexpr int sl = decltype(sc)::value;
-      if (slot == sl) {
+      const int j = sl - s0;
+      if (j >= 0 && j < ns) {
 #pragma unroll
         for (int m = 0; m < MPT; ++m) {
           const int idx = threadIdx.x + m * T;
-          if (idx < nmodes) reg[sl][m] = from_d2<V>(lds[lpad(idx)]);
+          if (idx < nmodes) reg[sl][m] = from_d2<V>(lds[lpad(j * nmodes + idx)]);
         }
       }
     });
@@ -377,24 +387,31 @@ __device__ __forceinline__ void fused_group(const PatchDev* P, const WorkItem& w
     __builtin_amdgcn_sched_barrier(0);
   }
 
-  // Inverse transforms of the outputs, written back over the input slots.
+  // Inverse transforms of the outputs, SL at a time, written back over the
+  // input slots.
 #pragma nounroll
-  for (int o = 0; o < Gr::nout; ++o) {
-    const int slot = Gr::out_slot[o];
+  for (int o0 = 0; o0 < Gr::nout; o0 += SL) {
+    const int no = Gr::nout - o0 < SL ? Gr::nout - o0 : SL;
     static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
       constexpr int sl = decltype(sc)::value;
-      if (slot == sl) {
 #pragma unroll
-        for (int m = 0; m < MPT; ++m) {
-          const int idx = threadIdx.x + m * T;
-          if (idx < nmodes) lds[lpad(idx)] = to_d2(reg[sl][m]);
+      for (int j = 0; j < SL; ++j) {
+        if (j < no && Gr::out_slot[o0 + j] == sl) {
+#pragma unroll
+          for (int m = 0; m < MPT; ++m) {
+            const int idx = threadIdx.x + m * T;
+            if (idx < nmodes) lds[lpad(j * nmodes + idx)] = to_d2(reg[sl][m]);
+          }
         }
       }
     });
     __syncthreads();
-    fft_lds<1, kMaxPtsFused>(lds, W, nz, F);
-    V* dst = base + Gr::in[slot] * cs;
-    for (int idx = threadIdx.x; idx < nmodes; idx += T) dst[idx] = from_d2<V>(lds[lpad(idx)]);
+    fft_lds<1, kMaxPtsFused>(lds, no * W, nz, F);
+    for (int j = 0; j < no; ++j) {
+      V* dst = base + Gr::in[Gr::out_slot[o0 + j]] * cs;
+      for (int idx = threadIdx.x; idx < nmodes; idx += T)
+        dst[idx] = from_d2<V>(lds[lpad(j * nmodes + idx)]);
+    }
     __syncthreads();
   }
 }

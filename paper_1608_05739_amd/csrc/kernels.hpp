@@ -23,6 +23,10 @@ constexpr int kMaxRadixZ = 8;     // largest radix of the z plans (fits kMaxPtsF
 constexpr int kLineBlockMax = 512;  // launch bound of the line-pass kernels
 constexpr int kFusedBlock = 512;    // launch bound (and block size) of the fused z pass
 
+// Slots (component tiles) the fused z pass transforms in one FFT at mpt modes
+// per thread: together they give each thread kMaxPtsFused points.
+constexpr int fused_slots(int mpt) { return kMaxPtsFused / mpt; }
+
 struct LaunchShape {
   int grid;
   int block;
