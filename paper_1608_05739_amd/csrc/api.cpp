@@ -373,6 +373,7 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
   const size_t first = items.size();
   size_t lds = 0;
   double bytes = 0.0;
+  int threads = 64;
   for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
     const PatchDev& P = plan->host_patches[pi];
     const int nlines = P.mx * P.ny;
@@ -389,6 +390,12 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
                   "fused path: nz = " + std::to_string(P.nz) + " does not fit one workgroup");
     int W = std::max(1, std::min(nlines, cap / P.nz));
     if (lines_cap > 0) W = std::min(W, lines_cap);
+    // the block shrinks to the threads the tile needs (mpt modes each, and
+    // kMaxPtsFused points of the sl stacked tiles each): small tiles run as
+    // several workgroups per CU, whose barriers do not stall each other
+    const int per = std::min(ps.mpt, points_per_thread(P.nz, kMaxPtsFused) / sl);
+    const int need = ((W * P.nz + per - 1) / per + 63) / 64 * 64;
+    threads = std::max(threads, std::min(block, need));
     lds = std::max(lds, static_cast<size_t>(lpad_size(sl * W * P.nz)) * sizeof(double2));
     ps.lines = std::max(ps.lines, W);
     for (int l = 0; l < nlines; l += W)
@@ -397,7 +404,7 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
     bytes += (plan->nin + 6) * cells * plan->elem;
   }
   ps.nitems = static_cast<int>(items.size() - first);
-  ps.shape = LaunchShape{ps.nitems, block, lds};
+  ps.shape = LaunchShape{ps.nitems, threads, lds};
   ps.bytes = bytes;
   ps.d_items = reinterpret_cast<WorkItem*>(first);
   *out = ps;
@@ -726,7 +733,7 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     for (size_t ci = 0; ci < cands.size() && st == PSATD_OK && e == hipSuccess; ++ci) {
       Pass& c = cands[ci].pass;
       std::vector<int> grids = {c.nitems};
-      for (int k : {1, 2, 4})
+      for (int k : {1, 2, 4, 8})
         if (k * plan->num_cus < c.nitems) grids.push_back(k * plan->num_cus);
       for (int g : grids) {
         c.shape.grid = g;
