@@ -355,7 +355,7 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
 }
 
 int fused_mpt(int precision, int ndim) {
-  if (precision == PSATD_FP32) return ndim == 2 ? 8 : 4;
+  if (precision == PSATD_FP32) return ndim == 2 ? 8 : 2;
   return ndim == 2 ? 4 : 2;
 }
 

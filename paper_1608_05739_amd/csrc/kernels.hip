@@ -575,7 +575,7 @@ hipError_t launch_line_pass(int kind, int precision, const LaunchShape& sh, hipS
 // Modes per thread compiled for each (precision, ndim): the transformed inputs
 // of a group stay in registers, so MPT * inputs * sizeof(complex) is bounded.
 bool fused_supported(int precision, int ndim, int mpt) {
-  if (precision == 0) return (ndim == 2 && mpt == 8) || (ndim == 3 && mpt == 4);
+  if (precision == 0) return (ndim == 2 && mpt == 8) || (ndim == 3 && mpt == 2);
   return (ndim == 2 && mpt == 4) || (ndim == 3 && mpt == 2);
 }
 
@@ -615,7 +615,7 @@ hipError_t launch_fused_z(int precision, int ndim, int src, int mpt, const Launc
     if (ndim == 2)
       return fused_dispatch<float, 2, 8>(src, sh, stream, patches, items, nitems,
                                          static_cast<float*>(ws), ph);
-    return fused_dispatch<float, 3, 4>(src, sh, stream, patches, items, nitems,
+    return fused_dispatch<float, 3, 2>(src, sh, stream, patches, items, nitems,
                                        static_cast<float*>(ws), ph);
   }
   if (ndim == 2)
@@ -717,7 +717,7 @@ hipError_t configure_kernel_attributes() {
   if ((r = set_attrs_for<float>()) != hipSuccess) e = r;
   if ((r = set_attrs_for<double>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 8>()) != hipSuccess) e = r;
-  if ((r = set_fused_attrs<float, 3, 4>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<float, 3, 2>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 3, 2>()) != hipSuccess) e = r;
   return e;
