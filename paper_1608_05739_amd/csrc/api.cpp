@@ -354,19 +354,20 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
   return ps;
 }
 
-int fused_mpt(int precision, int ndim) {
-  if (precision == PSATD_FP32) return ndim == 2 ? 8 : 2;
-  return ndim == 2 ? 4 : 2;
+// Modes per thread the fused pass is compiled for, smallest first.  Fewer
+// held inputs per thread leave room for more waves per SIMD; the larger
+// choice takes z lines the smaller one cannot hold.
+std::vector<int> fused_mpt_choices(int precision, int ndim) {
+  if (precision == PSATD_FP32) return ndim == 2 ? std::vector<int>{4, 8} : std::vector<int>{2, 4};
+  return {ndim == 2 ? 4 : 2};
 }
 
-// lines_cap > 0 limits the lines (z lines of one patch) per workgroup below
-// what LDS and registers allow (autotuning tries several).
-psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out,
-                             int lines_cap = 0) {
+psatd_status make_fused_pass_mpt(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out,
+                                 int lines_cap, int mpt) {
   Pass ps;
   ps.type = kFused;
   ps.name = "z_fused";
-  ps.mpt = fused_mpt(plan->cfg.precision, plan->ndim);
+  ps.mpt = mpt;
   const int block = kFusedBlock;
   const int modes = block * ps.mpt;
   const int sl = fused_slots(ps.mpt);
@@ -409,6 +410,21 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
   ps.d_items = reinterpret_cast<WorkItem*>(first);
   *out = ps;
   return PSATD_OK;
+}
+
+// The fused pass at `mpt` modes per thread, or (mpt = 0) at the smallest
+// compiled choice whose workgroups hold every patch's z lines.
+psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out,
+                             int lines_cap = 0, int mpt = 0) {
+  if (mpt > 0) return make_fused_pass_mpt(plan, items, out, lines_cap, mpt);
+  psatd_status st = PSATD_ERR_UNSUPPORTED_SIZE;
+  const size_t n0 = items.size();
+  for (int m : fused_mpt_choices(plan->cfg.precision, plan->ndim)) {
+    items.resize(n0);
+    st = make_fused_pass_mpt(plan, items, out, lines_cap, m);
+    if (st == PSATD_OK) return st;
+  }
+  return st;
 }
 
 Pass make_update_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
@@ -702,17 +718,23 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     };
     std::vector<Cand> cands;
     cands.push_back(Cand{ps, nullptr});
+    // (fused passes: also at every compiled modes-per-thread choice that holds
+    // the z lines)
+    std::vector<int> mpts = {0};
+    if (ps.type == kFused) mpts = fused_mpt_choices(plan->cfg.precision, plan->ndim);
     if (ps.type == kLine || ps.type == kFused) {
+      for (int m : mpts) {
+      if (e != hipSuccess) break;
       for (int R : {1, 2, 4, 8, 16, 32}) {
         std::vector<WorkItem> its;
         Pass c;
         if (ps.type == kLine) {
           c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
-        } else if (make_fused_pass(plan, its, &c, R) != PSATD_OK) {
+        } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
           continue;
         }
         bool seen = false;
-        for (const Cand& x : cands) seen = seen || x.pass.lines == c.lines;
+        for (const Cand& x : cands) seen = seen || (x.pass.lines == c.lines && x.pass.mpt == c.mpt);
         if (seen) continue;
         c.d_items = nullptr;
         if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
@@ -726,6 +748,7 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
         }
         c.d_items = d;
         cands.push_back(Cand{c, d});
+      }
       }
     }
     int best_c = 0, best_g = ps.shape.grid;

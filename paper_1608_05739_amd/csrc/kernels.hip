@@ -575,7 +575,8 @@ hipError_t launch_line_pass(int kind, int precision, const LaunchShape& sh, hipS
 // Modes per thread compiled for each (precision, ndim): the transformed inputs
 // of a group stay in registers, so MPT * inputs * sizeof(complex) is bounded.
 bool fused_supported(int precision, int ndim, int mpt) {
-  if (precision == 0) return (ndim == 2 && mpt == 8) || (ndim == 3 && mpt == 2);
+  if (precision == 0)
+    return (ndim == 2 && (mpt == 4 || mpt == 8)) || (ndim == 3 && (mpt == 2 || mpt == 4));
   return (ndim == 2 && mpt == 4) || (ndim == 3 && mpt == 2);
 }
 
@@ -612,11 +613,12 @@ hipError_t launch_fused_z(int precision, int ndim, int src, int mpt, const Launc
                           int nitems, void* ws, Physics ph) {
   if (!fused_supported(precision, ndim, mpt)) return hipErrorInvalidValue;
   if (precision == 0) {
+    float* w = static_cast<float*>(ws);
     if (ndim == 2)
-      return fused_dispatch<float, 2, 8>(src, sh, stream, patches, items, nitems,
-                                         static_cast<float*>(ws), ph);
-    return fused_dispatch<float, 3, 2>(src, sh, stream, patches, items, nitems,
-                                       static_cast<float*>(ws), ph);
+      return mpt == 4 ? fused_dispatch<float, 2, 4>(src, sh, stream, patches, items, nitems, w, ph)
+                      : fused_dispatch<float, 2, 8>(src, sh, stream, patches, items, nitems, w, ph);
+    return mpt == 2 ? fused_dispatch<float, 3, 2>(src, sh, stream, patches, items, nitems, w, ph)
+                    : fused_dispatch<float, 3, 4>(src, sh, stream, patches, items, nitems, w, ph);
   }
   if (ndim == 2)
     return fused_dispatch<double, 2, 4>(src, sh, stream, patches, items, nitems,
@@ -716,8 +718,10 @@ hipError_t configure_kernel_attributes() {
   hipError_t r;
   if ((r = set_attrs_for<float>()) != hipSuccess) e = r;
   if ((r = set_attrs_for<double>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<float, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 8>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 3, 2>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<float, 3, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 3, 2>()) != hipSuccess) e = r;
   return e;
