@@ -890,8 +890,8 @@ psatd_status build_plan(psatd_plan_s* plan) {
       for (size_t s = 0; s < r.size(); ++s) f.radix[s] = r[s];
       f.tw = reinterpret_cast<const double2*>(T + tw_off[L]);
     };
-    fill(P.fx, P.mx, 16);
-    fill(P.fy, P.ny, 16);
+    fill(P.fx, P.mx, kMaxPts);
+    fill(P.fy, P.ny, kMaxPts);
     fill(P.fz, P.nz, kMaxRadixZ);
     plan->host_patches.push_back(P);
 

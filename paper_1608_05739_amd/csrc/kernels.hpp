@@ -17,7 +17,7 @@ enum LineKind : int {
   kZInv = 5,  // contiguous z lines, inverse c2c in place (plain path)
 };
 
-constexpr int kMaxPts = 16;       // points per thread per FFT stage in the line passes
+constexpr int kMaxPts = 8;        // points per thread per FFT stage in the line passes
 constexpr int kMaxPtsFused = 8;   // ... in the fused z pass, which also holds its inputs
 constexpr int kMaxRadixZ = 8;     // largest radix of the z plans (fits kMaxPtsFused)
 constexpr int kLineBlockMax = 512;  // launch bound of the line-pass kernels
