@@ -391,11 +391,14 @@ psatd_status make_fused_pass_mpt(const psatd_plan_s* plan, std::vector<WorkItem>
                   "fused path: nz = " + std::to_string(P.nz) + " does not fit one workgroup");
     int W = std::max(1, std::min(nlines, cap / P.nz));
     if (lines_cap > 0) W = std::min(W, lines_cap);
-    // the block shrinks to the threads the tile needs (mpt modes each, and
-    // kMaxPtsFused points of the sl stacked tiles each): small tiles run as
-    // several workgroups per CU, whose barriers do not stall each other
-    const int per = std::min(ps.mpt, points_per_thread(P.nz, kMaxPtsFused) / sl);
-    const int need = ((W * P.nz + per - 1) / per + 63) / 64 * 64;
+    // the block shrinks to the threads the tile needs (at most mpt modes each,
+    // and at most ppt points of the sl stacked tiles each in a stage): small
+    // tiles run as several workgroups per CU, whose barriers do not stall
+    // each other
+    const int ppt = points_per_thread(P.nz, kMaxPtsFused);
+    const int t_modes = (W * P.nz + ps.mpt - 1) / ps.mpt;      // W nz <= T mpt
+    const int t_stage = (sl * W * P.nz + ppt - 1) / ppt;       // sl W nz <= T ppt
+    const int need = (std::max(t_modes, t_stage) + 63) / 64 * 64;
     threads = std::max(threads, std::min(block, need));
     lds = std::max(lds, static_cast<size_t>(lpad_size(sl * W * P.nz)) * sizeof(double2));
     ps.lines = std::max(ps.lines, W);
