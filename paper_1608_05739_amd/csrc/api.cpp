@@ -422,10 +422,14 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
   if (mpt > 0) return make_fused_pass_mpt(plan, items, out, lines_cap, mpt);
   psatd_status st = PSATD_ERR_UNSUPPORTED_SIZE;
   const size_t n0 = items.size();
+  const std::string before = g_last_error;  // a choice that does not fit is no error
   for (int m : fused_mpt_choices(plan->cfg.precision, plan->ndim)) {
     items.resize(n0);
     st = make_fused_pass_mpt(plan, items, out, lines_cap, m);
-    if (st == PSATD_OK) return st;
+    if (st == PSATD_OK) {
+      g_last_error = before;
+      return st;
+    }
   }
   return st;
 }
