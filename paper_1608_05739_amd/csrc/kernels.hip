@@ -77,18 +77,17 @@ __device__ __forceinline__ long long yline_start(const PatchDev* P, int l) {
 }
 
 // ------------------------------------------------------------------ r2c / c2r
-// After the forward complex FFT of z[m] = x[2m] + i x[2m+1] (length M):
-//   F[k] = E[k] + W^k O[k],  E = (Z[k] + conj Z[M-k])/2,  O = -i (Z[k] - conj Z[M-k])/2,
-//   F[M-k] = conj(E[k] - W^k O[k]),  W = exp(-2 pi i / (2M)).
-// Column 0 is packed as F[0] + i F[M] (both real).
-// The pairs (k, M-k) of a thread are taken in groups of kPairGroup: the post
-// twiddles of a group are requested before its LDS work, so their loads are in
-// flight together.  Distinct pairs touch distinct elements.
+// Runs op(row, k, W^k) for every pair (k, M - k), k = 0..M/2, of each of the
+// nl lines (row: the line's first logical LDS element).  A thread takes its
+// pairs kPairGroup at a time and requests their post-twiddles before their
+// LDS work, so the loads are in flight together; distinct pairs touch
+// distinct elements.
 constexpr int kPairGroup = 4;
 
-__device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
-  const int npair = M / 2 + 1;
-  Walk2 w(npair);
+template <typename Op>
+__device__ __forceinline__ void for_each_pair(int nl, int LS, int M, const double2* __restrict__ post,
+                                              Op&& op) {
+  Walk2 w(M / 2 + 1);
   while (w.hi < nl) {
     int row[kPairGroup], kk[kPairGroup];
     double2 wk[kPairGroup];
@@ -103,25 +102,32 @@ __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, co
       w.next();
     }
 #pragma unroll
-    for (int g = 0; g < kPairGroup; ++g) {
-      if (row[g] < 0) continue;
-      const int k = kk[g];
-      if (k == 0) {
-        const double2 z = lds[lpad(row[g])];
-        lds[lpad(row[g])] = make_double2(z.x + z.y, z.x - z.y);
-      } else {
-        const int km = M - k;
-        const double2 a = lds[lpad(row[g] + k)];
-        const double2 b = lds[lpad(row[g] + km)];
-        const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-        const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
-        const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
-        const double2 wo = cmul(wk[g], o);
-        lds[lpad(row[g] + k)] = cadd(e, wo);
-        if (km != k) lds[lpad(row[g] + km)] = cconj(csub(e, wo));
-      }
-    }
+    for (int g = 0; g < kPairGroup; ++g)
+      if (row[g] >= 0) op(row[g], kk[g], wk[g]);
   }
+}
+
+// After the forward complex FFT of z[m] = x[2m] + i x[2m+1] (length M):
+//   F[k] = E[k] + W^k O[k],  E = (Z[k] + conj Z[M-k])/2,  O = -i (Z[k] - conj Z[M-k])/2,
+//   F[M-k] = conj(E[k] - W^k O[k]),  W = exp(-2 pi i / (2M)).
+// Column 0 is packed as F[0] + i F[M] (both real).
+__device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
+  for_each_pair(nl, LS, M, post, [&](int row, int k, double2 wk) __attribute__((always_inline)) {
+    if (k == 0) {
+      const double2 z = lds[lpad(row)];
+      lds[lpad(row)] = make_double2(z.x + z.y, z.x - z.y);
+      return;
+    }
+    const int km = M - k;
+    const double2 a = lds[lpad(row + k)];
+    const double2 b = lds[lpad(row + km)];
+    const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    const double2 d = make_double2(a.x - b.x, a.y + b.y);  // a - conj(b)
+    const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);  // -i d / 2
+    const double2 wo = cmul(wk, o);
+    lds[lpad(row + k)] = cadd(e, wo);
+    if (km != k) lds[lpad(row + km)] = cconj(csub(e, wo));
+  });
   __syncthreads();
 }
 
@@ -129,41 +135,22 @@ __device__ __forceinline__ void r2c_post(double2* lds, int nl, int LS, int M, co
 // Z'[M-k] = conj(p) + i W^k conj(m) with p = F[k] + conj F[M-k], m = F[k] - conj F[M-k];
 // column 0: Z'[0] = (F0 + FM) + i (F0 - FM).
 __device__ __forceinline__ void c2r_pre(double2* lds, int nl, int LS, int M, const double2* __restrict__ post) {
-  const int npair = M / 2 + 1;
-  Walk2 w(npair);
-  while (w.hi < nl) {
-    int row[kPairGroup], kk[kPairGroup];
-    double2 wk[kPairGroup];
-#pragma unroll
-    for (int g = 0; g < kPairGroup; ++g) {
-      row[g] = -1;
-      if (w.hi < nl) {
-        row[g] = w.hi * LS;
-        kk[g] = w.lo;
-        wk[g] = gload(post, w.lo);
-      }
-      w.next();
+  for_each_pair(nl, LS, M, post, [&](int row, int k, double2 wk) __attribute__((always_inline)) {
+    if (k == 0) {
+      const double2 x = lds[lpad(row)];
+      lds[lpad(row)] = make_double2(x.x + x.y, x.x - x.y);
+      return;
     }
-#pragma unroll
-    for (int g = 0; g < kPairGroup; ++g) {
-      if (row[g] < 0) continue;
-      const int k = kk[g];
-      if (k == 0) {
-        const double2 x = lds[lpad(row[g])];
-        lds[lpad(row[g])] = make_double2(x.x + x.y, x.x - x.y);
-      } else {
-        const int km = M - k;
-        const double2 a = lds[lpad(row[g] + k)];
-        const double2 b = lds[lpad(row[g] + km)];
-        const double2 p = make_double2(a.x + b.x, a.y - b.y);
-        const double2 m = make_double2(a.x - b.x, a.y + b.y);
-        const double2 t1 = cmul(cconj(wk[g]), m);
-        const double2 t2 = cmul(wk[g], cconj(m));
-        lds[lpad(row[g] + k)] = make_double2(p.x - t1.y, p.y + t1.x);
-        if (km != k) lds[lpad(row[g] + km)] = make_double2(p.x - t2.y, -p.y + t2.x);
-      }
-    }
-  }
+    const int km = M - k;
+    const double2 a = lds[lpad(row + k)];
+    const double2 b = lds[lpad(row + km)];
+    const double2 p = make_double2(a.x + b.x, a.y - b.y);
+    const double2 m = make_double2(a.x - b.x, a.y + b.y);
+    const double2 t1 = cmul(cconj(wk), m);
+    const double2 t2 = cmul(wk, cconj(m));
+    lds[lpad(row + k)] = make_double2(p.x - t1.y, p.y + t1.x);
+    if (km != k) lds[lpad(row + km)] = make_double2(p.x - t2.y, -p.y + t2.x);
+  });
   __syncthreads();
 }
 
