@@ -225,8 +225,10 @@ __device__ __forceinline__ void lds_stage(double2* lds, int L, int nl, int LS, i
   // Twiddles first, for every butterfly slot (k < Ns keeps the index inside
   // the table even for slots past the tile), so that they are in flight
   // during the LDS reads; k = 0 takes tw[0] = 1, which multiplies exactly.
+  // The first stage (Ns = 1) has k = 0 throughout and needs none.
+  const bool twiddled = Ns > 1;
   double2 wt[BPT];
-  {
+  if (twiddled) {
     int kk = k;
 #pragma unroll
     for (int t = 0; t < BPT; ++t) {
@@ -252,7 +254,7 @@ __device__ __forceinline__ void lds_stage(double2* lds, int L, int nl, int LS, i
   }
 #pragma unroll
   for (int t = 0; t < BPT; ++t) {
-    if (obase[t] >= 0) {
+    if (twiddled && obase[t] >= 0) {
       double2 u = wt[t];
       if constexpr (SIGN > 0) u.y = -u.y;
       double2 uq = u;
