@@ -397,7 +397,7 @@ def main():
         print(json.dumps(data, indent=1, sort_keys=True))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
+        print(f"bench.py runs on one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -358,7 +358,7 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
 // held inputs per thread leave room for more waves per SIMD; the larger
 // choice takes z lines the smaller one cannot hold.
 std::vector<int> fused_mpt_choices(int precision, int ndim) {
-  if (precision == PSATD_FP32) return ndim == 2 ? std::vector<int>{4, 8} : std::vector<int>{2, 4};
+  if (precision == PSATD_FP32) return ndim == 2 ? std::vector<int>{2, 4, 8} : std::vector<int>{2, 4};
   return {ndim == 2 ? 4 : 2};
 }
 

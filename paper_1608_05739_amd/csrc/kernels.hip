@@ -563,7 +563,7 @@ hipError_t launch_line_pass(int kind, int precision, const LaunchShape& sh, hipS
 // of a group stay in registers, so MPT * inputs * sizeof(complex) is bounded.
 bool fused_supported(int precision, int ndim, int mpt) {
   if (precision == 0)
-    return (ndim == 2 && (mpt == 4 || mpt == 8)) || (ndim == 3 && (mpt == 2 || mpt == 4));
+    return (ndim == 2 && (mpt == 2 || mpt == 4 || mpt == 8)) || (ndim == 3 && (mpt == 2 || mpt == 4));
   return (ndim == 2 && mpt == 4) || (ndim == 3 && mpt == 2);
 }
 
@@ -602,8 +602,9 @@ hipError_t launch_fused_z(int precision, int ndim, int src, int mpt, const Launc
   if (precision == 0) {
     float* w = static_cast<float*>(ws);
     if (ndim == 2)
-      return mpt == 4 ? fused_dispatch<float, 2, 4>(src, sh, stream, patches, items, nitems, w, ph)
-                      : fused_dispatch<float, 2, 8>(src, sh, stream, patches, items, nitems, w, ph);
+      return mpt == 2   ? fused_dispatch<float, 2, 2>(src, sh, stream, patches, items, nitems, w, ph)
+             : mpt == 4 ? fused_dispatch<float, 2, 4>(src, sh, stream, patches, items, nitems, w, ph)
+                        : fused_dispatch<float, 2, 8>(src, sh, stream, patches, items, nitems, w, ph);
     return mpt == 2 ? fused_dispatch<float, 3, 2>(src, sh, stream, patches, items, nitems, w, ph)
                     : fused_dispatch<float, 3, 4>(src, sh, stream, patches, items, nitems, w, ph);
   }
@@ -705,6 +706,7 @@ hipError_t configure_kernel_attributes() {
   hipError_t r;
   if ((r = set_attrs_for<float>()) != hipSuccess) e = r;
   if ((r = set_attrs_for<double>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<float, 2, 2>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 8>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 3, 2>()) != hipSuccess) e = r;
