@@ -428,8 +428,10 @@ def main():
     cells = w.cells
 
     # ------------------------------------------------ FP32 storage, fused path
+    # radix-4 generic line passes where every generic line is short (<= 256)
+    radix4 = max(max(p.nx // 2, p.ny) for p in w.patches) <= 256
     plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", graph=True,
-                   autotune=True)
+                   autotune=True, radix4_lines=radix4)
     log("[bench] fp32 fused plan:\n" + plan.info)
     E, B, J, ro, rn = device_fields(w, plan, np.float32)
     # one-step parity spot check on the same inputs (before timing mutates E, B)
@@ -484,7 +486,7 @@ def main():
 
     cfg = {"workload": w.name, "cells": cells, "patches": len(w.patches), "steps_per_config": default_steps,
            "source_form": mode, "storage": "f32", "arithmetic": "f64", "path": "fused",
-           "graph": True}
+           "graph": True, "generic_line_radix": 4 if radix4 else 8}
     out = {
         "metric": METRIC,
         "value": value,

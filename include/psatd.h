@@ -83,6 +83,14 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
  * PSATD_ERR_INVALID_ARG when c dt |k|max / 2 > 1 for a patch (its Courant
  * condition; |k|max over the patch's k table). */
 #define PSATD_FLAG_PSTD 0x20u
+/* The generic line passes (any size other than the 4096 x 4096 2D grid)
+ * factor each line into radix-4 stages (then one radix-2 and the radix-3
+ * stages) at 4 points per thread, instead of the default radices of at most 8
+ * at 8 points per thread.  Half the registers, twice the waves per SIMD:
+ * faster on short lines (2D patches with sides of a few hundred cells),
+ * slower on long ones.  The factorization rounds differently, so results
+ * differ from the default ones in the last bits. */
+#define PSATD_FLAG_RADIX4_LINES 0x40u
 
 typedef struct {
   int32_t ndim;  /* 2: (x, z) plane, n[1] must be 1;  3: (x, y, z)                   */

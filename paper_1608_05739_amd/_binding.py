@@ -30,6 +30,7 @@ FLAG_NO_WORKSPACE = 0x4
 FLAG_GENERIC_KERNELS = 0x8
 FLAG_CENTERED_STENCIL = 0x10
 FLAG_PSTD = 0x20
+FLAG_RADIX4_LINES = 0x40
 FDTD_SCHEME = {"yee": 0, "ckc": 1}
 
 EXPORTED_SYMBOLS = (
@@ -162,7 +163,7 @@ def as_patch(p) -> Patch:
 
 def make_config(precision="fp32", source_mode="vacuum", path="fused", order=0, c=1.0, eps0=1.0,
                 *, autotune=False, graph=False, allocate_workspace=True, generic_kernels=False,
-                centered_stencil=False, pstd=False) -> Config:
+                centered_stencil=False, pstd=False, radix4_lines=False) -> Config:
     cfg = Config()
     cfg.precision = PRECISION[precision]
     cfg.source_mode = SOURCE_MODE[source_mode]
@@ -174,7 +175,8 @@ def make_config(precision="fp32", source_mode="vacuum", path="fused", order=0, c
                  | (0 if allocate_workspace else FLAG_NO_WORKSPACE)
                  | (FLAG_GENERIC_KERNELS if generic_kernels else 0)
                  | (FLAG_CENTERED_STENCIL if centered_stencil else 0)
-                 | (FLAG_PSTD if pstd else 0))
+                 | (FLAG_PSTD if pstd else 0)
+                 | (FLAG_RADIX4_LINES if radix4_lines else 0))
     return cfg
 
 
@@ -212,13 +214,14 @@ class Plan:
     Component buffers are flat tensors holding every patch at its offset
     (by default the patches are packed in order, see :attr:`offsets`).
     ``pstd=True`` runs the PSTD contrast solver instead (leapfrog: B holds B
-    at half-integer times; source_mode "vacuum" or "j").
+    at half-integer times; source_mode "vacuum" or "j").  ``radix4_lines=True``
+    runs the generic line passes as radix-4 stages at 4 points per thread.
     """
 
     def __init__(self, patches: Sequence, *, precision="fp32", source_mode="vacuum",
                  path="fused", order=0, c=1.0, eps0=1.0, autotune=False, graph=False,
                  device=0, allocate_workspace=True, generic_kernels=False,
-                 centered_stencil=False, pstd=False):
+                 centered_stencil=False, pstd=False, radix4_lines=False):
         self._lib = load_library()
         self._plan = None
         ps = [as_patch(p) for p in patches]
@@ -246,7 +249,7 @@ class Plan:
         cfg = make_config(precision, source_mode, path, order, c, eps0, autotune=autotune,
                           graph=graph, allocate_workspace=allocate_workspace,
                           generic_kernels=generic_kernels, centered_stencil=centered_stencil,
-                          pstd=pstd)
+                          pstd=pstd, radix4_lines=radix4_lines)
         handle = ctypes.c_void_p()
         _check(self._lib, self._lib.psatd_plan(ctypes.byref(cfg), descs, len(ps), int(device),
                                                 ctypes.byref(handle)))

@@ -38,13 +38,13 @@ bool even_2a3b(int64_t n) {
 }
 
 // Radix schedule of a complex length L = 2^a 3^b (L = 1: no stages), largest
-// radices first, none above max_radix (16 or 8).
+// radices first, none above max_radix (16, 8 or 4).
 std::vector<int> radix_plan(int L, int max_radix) {
   int a = 0, b = 0;
   while (L % 2 == 0) { L /= 2; ++a; }
   while (L % 3 == 0) { L /= 3; ++b; }
   std::vector<int> r;
-  const int big = max_radix >= 16 ? 4 : 3;
+  const int big = max_radix >= 16 ? 4 : (max_radix >= 8 ? 3 : 2);
   while (a >= big) { r.push_back(1 << big); a -= big; }
   if (a == 3) r.push_back(8);
   if (a == 2) r.push_back(4);
@@ -59,9 +59,9 @@ bool has_radix3(int L) { return L % 3 == 0; }
 // radix-3 stages hold 3 * floor(maxpts / 3).
 int points_per_thread(int L, int maxpts) { return has_radix3(L) ? 3 * (maxpts / 3) : maxpts; }
 
-// Threads needed so that no thread holds more than kMaxPts points in a stage.
-int threads_for(int points, int L) {
-  const int per = points_per_thread(L, kMaxPts);
+// Threads needed so that no thread holds more than ppt points in a stage.
+int threads_for(int points, int L, int ppt) {
+  const int per = points_per_thread(L, ppt);
   int t = (points + per - 1) / per;
   t = ((t + 63) / 64) * 64;
   return std::max(64, t);
@@ -119,7 +119,8 @@ struct Pass {
   WorkItem* d_items = nullptr;
   int nitems = 0;
   double bytes = 0.0;
-  int mpt = 0;
+  int mpt = 0;             // fused pass: modes per thread
+  int ppt = 0;             // line passes: points per thread per FFT stage
   double tuned_ms = -1.0;  // mean launch time at the chosen grid (autotune), else -1
   std::vector<int> comps;  // line passes: the components they transform
   int lines = 0;           // line passes: lines per workgroup (the tile)
@@ -227,7 +228,8 @@ psatd_status validate(const psatd_config* cfg, const psatd_patch_desc* patches, 
   if (!(cfg->eps0 > 0.0) || !std::isfinite(cfg->eps0))
     return fail(PSATD_ERR_INVALID_ARG, "eps0 must be > 0");
   if (cfg->flags & ~(PSATD_FLAG_AUTOTUNE | PSATD_FLAG_GRAPH | PSATD_FLAG_NO_WORKSPACE |
-                     PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_CENTERED_STENCIL | PSATD_FLAG_PSTD))
+                     PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_CENTERED_STENCIL | PSATD_FLAG_PSTD |
+                     PSATD_FLAG_RADIX4_LINES))
     return fail(PSATD_ERR_INVALID_ARG, "unknown flag bits");
   if ((cfg->flags & PSATD_FLAG_PSTD) && cfg->source_mode == PSATD_SOURCES_RHO)
     return fail(PSATD_ERR_INVALID_ARG, "PSTD takes J only: source_mode VACUUM or SOURCES_J");
@@ -308,11 +310,18 @@ void line_geometry(int kind, const PatchDev& P, int* nlines, int* L) {
 }
 
 // Build a line pass over all patches for the given components.
+// Points per thread of the plan's generic line passes.
+int line_ppt(const psatd_plan_s* plan) {
+  return (plan->cfg.flags & PSATD_FLAG_RADIX4_LINES) ? 4 : kMaxPts;
+}
+
 Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
                     std::vector<WorkItem>& items, int lines_override = 0) {
+  const int ppt = line_ppt(plan);
   Pass ps;
   ps.type = kLine;
   ps.line_kind = kind;
+  ps.ppt = ppt;
   ps.name = line_pass_name(kind);
   const bool transposing = kind == kXFwd || kind == kXInv || kind == kYFwd || kind == kYInv;
   const int want = lines_override > 0 ? lines_override : (plan->elem == 4 ? 8 : 4);
@@ -335,9 +344,9 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
     R = std::min(R, nlines);
     // LDS holds R lines (<= 8192 points, 136 KB padded) and 512 threads own
     // every stage's points
-    const int max_pts = std::min(8192, kLineBlockMax * points_per_thread(L, kMaxPts));
+    const int max_pts = std::min(8192, kLineBlockMax * points_per_thread(L, ppt));
     R = std::max(1, std::min(R, max_pts / L));
-    block = std::max(block, threads_for(R * L, L));
+    block = std::max(block, threads_for(R * L, L, ppt));
     lds = std::max(lds, static_cast<size_t>(lpad_size(R * L)) * sizeof(double2));
     ps.lines = std::max(ps.lines, R);
     for (int c : comps)
@@ -462,7 +471,9 @@ Pass make_update_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
 // holds every item, and in each FFT stage the block owns all butterflies
 // within the per-thread register budget.
 psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkItem* items) {
-  const int maxpts = ps.type == kFused ? kMaxPtsFused : kMaxPts;
+  const int maxpts = ps.type == kFused ? kMaxPtsFused : ps.ppt;
+  if (ps.type == kLine && !line_ppt_supported(ps.ppt))
+    return fail(PSATD_ERR_STATE, std::string(ps.name) + ": points per thread not compiled");
   for (int i = 0; i < ps.nitems; ++i) {
     const WorkItem& w = items[i];
     if (w.patch < 0 || w.patch >= static_cast<int>(plan->host_patches.size()))
@@ -508,13 +519,16 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
     if (static_cast<long long>(lpad_size(static_cast<int>(pts))) * static_cast<long long>(sizeof(double2)) >
         static_cast<long long>(ps.shape.lds_bytes))
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item exceeds LDS");
-    if (ps.type == kLine && pts > static_cast<long long>(ps.shape.block) * kMaxPts)
+    if (ps.type == kLine && pts > static_cast<long long>(ps.shape.block) * ps.ppt)
       return fail(PSATD_ERR_STATE, std::string(ps.name) + ": tile exceeds the loads a thread holds");
     if (ps.type == kFused &&
         static_cast<long long>(w.count) * L > static_cast<long long>(ps.shape.block) * ps.mpt)
       return fail(PSATD_ERR_STATE, "z_fused: modes exceed registers");
-    for (int s = 0; s < f->nstages; ++s) {
-      const int r = f->radix[s];
+    // the stages the kernel runs: the plan's radices, or at 4 points per
+    // thread the radix-4 schedule it derives from the length
+    std::vector<int> radices(f->radix, f->radix + f->nstages);
+    if (ps.type == kLine && ps.ppt == 4) radices = radix_plan(L, 4);
+    for (int r : radices) {
       if (r > maxpts) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": radix too large");
       const long long bpt = maxpts / r;
       if (pts / r > bpt * ps.shape.block)
@@ -582,8 +596,8 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
   const Physics ph{plan->cfg.c, plan->cfg.eps0};
   switch (ps.type) {
     case kLine:
-      e = launch_line_pass(ps.line_kind, plan->cfg.precision, ps.shape, s, plan->d_patches,
-                           ps.d_items, ps.nitems, f, plan->ws);
+      e = launch_line_pass(ps.line_kind, plan->cfg.precision, ps.ppt, ps.shape, s,
+                           plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
       break;
     case kFused:
       e = launch_fused_z(plan->cfg.precision, plan->ndim, plan->src_form, ps.mpt, ps.shape,
@@ -726,11 +740,11 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     std::vector<Cand> cands;
     cands.push_back(Cand{ps, nullptr});
     // (fused passes: also at every compiled modes-per-thread choice that holds
-    // the z lines)
-    std::vector<int> mpts = {0};
-    if (ps.type == kFused) mpts = fused_mpt_choices(plan->cfg.precision, plan->ndim);
+    // the z lines; these run the same arithmetic per line)
+    std::vector<int> vars = {0};
+    if (ps.type == kFused) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
     if (ps.type == kLine || ps.type == kFused) {
-      for (int m : mpts) {
+      for (int m : vars) {
       if (e != hipSuccess) break;
       for (int R : {1, 2, 4, 8, 16, 32}) {
         std::vector<WorkItem> its;
@@ -741,7 +755,8 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
           continue;
         }
         bool seen = false;
-        for (const Cand& x : cands) seen = seen || (x.pass.lines == c.lines && x.pass.mpt == c.mpt);
+        for (const Cand& x : cands)
+          seen = seen || (x.pass.lines == c.lines && x.pass.mpt == c.mpt && x.pass.ppt == c.ppt);
         if (seen) continue;
         c.d_items = nullptr;
         if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
@@ -998,9 +1013,9 @@ psatd_status build_plan(psatd_plan_s* plan) {
   plan->info += buf;
   for (const Pass& ps : plan->passes) {
     std::snprintf(buf, sizeof(buf),
-                  "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d lines=%d bytes=%.0f%s\n",
+                  "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d ppt=%d lines=%d bytes=%.0f%s\n",
                   ps.name, ps.nitems, ps.shape.grid, ps.shape.block, ps.shape.lds_bytes, ps.mpt,
-                  ps.lines, ps.bytes, ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
+                  ps.ppt, ps.lines, ps.bytes, ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
     plan->info += buf;
   }
   return PSATD_OK;

@@ -155,7 +155,29 @@ __device__ __forceinline__ void c2r_pre(double2* lds, int nl, int LS, int M, con
 }
 
 // ------------------------------------------------------------------ line pass
-template <typename S, int KIND>
+// The line passes at PPT = 4 points per thread run radix-4 stages (then one
+// radix-2 and the radix-3 stages), derived from the line length in the same
+// order as the planner's radix_plan(L, 4); at PPT = 8 they run the plan's
+// stored radices (at most 8).
+template <int SIGN>
+__device__ __forceinline__ void fft_lds_r4(double2* lds, int nl, int LS, const FFTPlanDev* __restrict__ f) {
+  const int L = f->n;
+  int n = L, b = 0;
+  while (n % 3 == 0) {
+    n /= 3;
+    ++b;
+  }
+  int a = __builtin_ctz(n);
+  int Ns = 1;
+  for (; a >= 2; a -= 2, Ns *= 4) lds_stage<4, SIGN, 4>(lds, L, nl, LS, Ns, f->tw);
+  if (a == 1) {
+    lds_stage<2, SIGN, 4>(lds, L, nl, LS, Ns, f->tw);
+    Ns *= 2;
+  }
+  for (; b > 0; --b, Ns *= 3) lds_stage<3, SIGN, 4>(lds, L, nl, LS, Ns, f->tw);
+}
+
+template <typename S, int KIND, int PPT>
 __global__ void __launch_bounds__(kLineBlockMax)
 line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
                  int nitems, FieldPtrs fields, S* __restrict__ ws) {
@@ -182,16 +204,16 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
     V* spec_out = (KIND == kXFwd || KIND == kXInv || KIND == kYInv) ? blk_x : blk_z;  // stores
 
     // ---------------- load
-    // Every element a thread owns (at most kMaxPts) is requested before the
+    // Every element a thread owns (at most PPT) is requested before the
     // first one is written to LDS, so a thread's loads are in flight together.
-    V r[kMaxPts];
+    V r[PPT];
     if constexpr (KIND == kXInv || KIND == kYInv) {
       // strided side: element n of tile line r goes to LDS element r LS + n
       const TileMap tm = tile_map(KIND, P);
-      int dst[kMaxPts];
+      int dst[PPT];
       Walk2 w(nl);
 #pragma unroll
-      for (int t = 0; t < kMaxPts; ++t) {
+      for (int t = 0; t < PPT; ++t) {
         dst[t] = -1;
         if (w.hi < L) {
           r[t] = spec[tile_offset(tm, l0 + w.lo, w.hi)];
@@ -200,14 +222,14 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
         w.next();
       }
 #pragma unroll
-      for (int t = 0; t < kMaxPts; ++t)
+      for (int t = 0; t < PPT; ++t)
         if (dst[t] >= 0) lds[lpad(dst[t])] = to_d2(r[t]);
     } else {
       // lines of the tile in LDS order: element idx = (line, n) sits at idx
       if constexpr (KIND == kYFwd) {
         Walk2 w(L);
 #pragma unroll
-        for (int t = 0; t < kMaxPts; ++t) {
+        for (int t = 0; t < PPT; ++t) {
           if (w.hi < nl) r[t] = spec[yline_start(P, l0 + w.hi) + w.lo];
           w.next();
         }
@@ -219,13 +241,13 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
                            : spec;
         src += (long long)l0 * L;
 #pragma unroll
-        for (int t = 0; t < kMaxPts; ++t) {
+        for (int t = 0; t < PPT; ++t) {
           const int idx = threadIdx.x + t * T;
           if (idx < total) r[t] = src[idx];
         }
       }
 #pragma unroll
-      for (int t = 0; t < kMaxPts; ++t) {
+      for (int t = 0; t < PPT; ++t) {
         const int idx = threadIdx.x + t * T;
         if (idx < total) lds[lpad(idx)] = to_d2(r[t]);
       }
@@ -233,7 +255,8 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
     __syncthreads();
 
     if constexpr (KIND == kXInv) c2r_pre(lds, nl, LS, L, P->post);
-    fft_lds<SIGN, kMaxPts>(lds, nl, LS, F);
+    if constexpr (PPT == 4) fft_lds_r4<SIGN>(lds, nl, LS, F);
+    else fft_lds<SIGN, PPT>(lds, nl, LS, F);
     if constexpr (KIND == kXFwd) r2c_post(lds, nl, LS, L, P->post);
 
     // ---------------- store
@@ -516,47 +539,53 @@ __global__ void ktable_kernel(double* k, int n, double d, int count, int packed_
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename S>
+template <typename S, int PPT>
 static hipError_t line_dispatch(int kind, const LaunchShape& sh, hipStream_t stream,
                                 const PatchDev* p, const WorkItem* it, int n, const FieldPtrs& f,
                                 S* ws) {
   switch (kind) {
     case kXFwd:
-      hipLaunchKernelGGL((line_pass_kernel<S, kXFwd>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
-                         stream, p, it, n, f, ws);
+      hipLaunchKernelGGL((line_pass_kernel<S, kXFwd, PPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, f, ws);
       break;
     case kXInv:
-      hipLaunchKernelGGL((line_pass_kernel<S, kXInv>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
-                         stream, p, it, n, f, ws);
+      hipLaunchKernelGGL((line_pass_kernel<S, kXInv, PPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, f, ws);
       break;
     case kYFwd:
-      hipLaunchKernelGGL((line_pass_kernel<S, kYFwd>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
-                         stream, p, it, n, f, ws);
+      hipLaunchKernelGGL((line_pass_kernel<S, kYFwd, PPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, f, ws);
       break;
     case kYInv:
-      hipLaunchKernelGGL((line_pass_kernel<S, kYInv>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
-                         stream, p, it, n, f, ws);
+      hipLaunchKernelGGL((line_pass_kernel<S, kYInv, PPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, f, ws);
       break;
     case kZFwd:
-      hipLaunchKernelGGL((line_pass_kernel<S, kZFwd>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
-                         stream, p, it, n, f, ws);
+      hipLaunchKernelGGL((line_pass_kernel<S, kZFwd, PPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, f, ws);
       break;
     default:
-      hipLaunchKernelGGL((line_pass_kernel<S, kZInv>), dim3(sh.grid), dim3(sh.block), sh.lds_bytes,
-                         stream, p, it, n, f, ws);
+      hipLaunchKernelGGL((line_pass_kernel<S, kZInv, PPT>), dim3(sh.grid), dim3(sh.block),
+                         sh.lds_bytes, stream, p, it, n, f, ws);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_line_pass(int kind, int precision, const LaunchShape& sh, hipStream_t stream,
-                            const PatchDev* patches, const WorkItem* items, int nitems,
-                            const FieldPtrs& fields, void* ws) {
-  if (precision == 0)
-    return line_dispatch<float>(kind, sh, stream, patches, items, nitems, fields,
-                                static_cast<float*>(ws));
-  return line_dispatch<double>(kind, sh, stream, patches, items, nitems, fields,
-                               static_cast<double*>(ws));
+bool line_ppt_supported(int ppt) { return ppt == 4 || ppt == kMaxPts; }
+
+hipError_t launch_line_pass(int kind, int precision, int ppt, const LaunchShape& sh,
+                            hipStream_t stream, const PatchDev* patches, const WorkItem* items,
+                            int nitems, const FieldPtrs& fields, void* ws) {
+  if (!line_ppt_supported(ppt)) return hipErrorInvalidValue;
+  if (precision == 0) {
+    float* w = static_cast<float*>(ws);
+    return ppt == 4 ? line_dispatch<float, 4>(kind, sh, stream, patches, items, nitems, fields, w)
+                    : line_dispatch<float, kMaxPts>(kind, sh, stream, patches, items, nitems, fields, w);
+  }
+  double* w = static_cast<double*>(ws);
+  return ppt == 4 ? line_dispatch<double, 4>(kind, sh, stream, patches, items, nitems, fields, w)
+                  : line_dispatch<double, kMaxPts>(kind, sh, stream, patches, items, nitems, fields, w);
 }
 
 // Modes per thread compiled for each (precision, ndim): the transformed inputs
@@ -668,7 +697,7 @@ hipError_t launch_ktable(double* k, int n, double d, int count, int packed_x,
   return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, int PPT>
 static hipError_t set_attrs_for() {
   const int lim = 160 * 1024;
   hipError_t e = hipSuccess;
@@ -676,12 +705,12 @@ static hipError_t set_attrs_for() {
     hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (r != hipSuccess) e = r;
   };
-  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kXFwd>));
-  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kXInv>));
-  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kYFwd>));
-  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kYInv>));
-  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kZFwd>));
-  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kZInv>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kXFwd, PPT>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kXInv, PPT>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kYFwd, PPT>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kYInv, PPT>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kZFwd, PPT>));
+  set(reinterpret_cast<const void*>(&line_pass_kernel<S, kZInv, PPT>));
   return e;
 }
 
@@ -704,8 +733,10 @@ static hipError_t set_fused_attrs() {
 hipError_t configure_kernel_attributes() {
   hipError_t e = hipSuccess;
   hipError_t r;
-  if ((r = set_attrs_for<float>()) != hipSuccess) e = r;
-  if ((r = set_attrs_for<double>()) != hipSuccess) e = r;
+  if ((r = set_attrs_for<float, 4>()) != hipSuccess) e = r;
+  if ((r = set_attrs_for<float, kMaxPts>()) != hipSuccess) e = r;
+  if ((r = set_attrs_for<double, 4>()) != hipSuccess) e = r;
+  if ((r = set_attrs_for<double, kMaxPts>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 2>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 2, 8>()) != hipSuccess) e = r;

@@ -33,9 +33,12 @@ struct LaunchShape {
   size_t lds_bytes;
 };
 
-hipError_t launch_line_pass(int kind, int precision, const LaunchShape& sh, hipStream_t stream,
-                            const PatchDev* patches, const WorkItem* items, int nitems,
-                            const FieldPtrs& fields, void* ws);
+// ppt: points per thread per FFT stage, 4 (radix-4 stages) or kMaxPts (the
+// plan's radices); the block must give every element of a tile a thread slot.
+hipError_t launch_line_pass(int kind, int precision, int ppt, const LaunchShape& sh,
+                            hipStream_t stream, const PatchDev* patches, const WorkItem* items,
+                            int nitems, const FieldPtrs& fields, void* ws);
+bool line_ppt_supported(int ppt);
 
 // Fused z pass: forward FFT of the inputs along z, per-mode update, inverse
 // FFT of E', B' along z, all in one launch.  mpt = modes per thread.

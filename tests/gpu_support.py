@@ -57,7 +57,7 @@ def rel_l2(a, b):
 
 
 def run_gpu(w, precision, path, steps, form="rho", order=0, graph=False, patches=None,
-            E0=None, B0=None, schedule=None):
+            E0=None, B0=None, schedule=None, radix4_lines=False):
     """Run ``steps`` steps of workload ``w`` on the GPU; returns (E, B) per patch (float64)."""
     import torch
     patches = patches if patches is not None else w.patches
@@ -67,7 +67,7 @@ def run_gpu(w, precision, path, steps, form="rho", order=0, graph=False, patches
     sources = w.sources
     mode = ("rho" if form == "rho" else "j") if sources else "vacuum"
     plan = pk.Plan(patches, precision=precision, source_mode=mode, path=path, order=order,
-                   graph=graph)
+                   graph=graph, radix4_lines=radix4_lines)
     E = fields_to_device(E0, plan, precision)
     B = fields_to_device(B0, plan, precision)
     if not sources:

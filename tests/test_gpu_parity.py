@@ -93,6 +93,32 @@ def test_order_p(order):
     assert err < TOL["fp64"]
 
 
+# ----------------------------------------------------------------- radix-4 line passes
+# PSATD_FLAG_RADIX4_LINES: the generic line passes as radix-4 (then radix-2 and
+# radix-3) stages at 4 points per thread; lengths with radix-3 factors, odd
+# powers of two and length-1 x transforms included.
+@pytest.mark.parametrize("index,shape", [(1, (12, 18)), (1, (36, 24)), (1, (96, 64)), (1, (2, 4)),
+                                         (1, (64, 96)), (2, (12, 8, 18)), (2, (16, 16, 16)),
+                                         (2, (6, 12, 8))])
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp64", "fused"),
+                                            ("fp32", "fused")])
+def test_radix4_line_passes(index, shape, precision, path):
+    w = _w(index, shape, 3)
+    say(f"radix-4 lines {shape} {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps, radix4_lines=True),
+                  run_oracle(w, precision, w.steps))
+    say(f"  rel L2 = {err:.3e}")
+    assert err < TOL[precision]
+
+
+def test_radix4_line_passes_batched():
+    w = fixtures.workload(3, npatches=24, steps=3)
+    err = compare(run_gpu(w, "fp32", "fused", w.steps, radix4_lines=True),
+                  run_oracle(w, "fp32", w.steps))
+    say(f"radix-4 lines, 24 batched patches: rel L2 = {err:.3e}")
+    assert err < TOL["fp32"]
+
+
 # ----------------------------------------------------------------- batched patches
 def test_batched_patches_workload3_subset():
     w = fixtures.workload(3, npatches=24, steps=3)

@@ -137,6 +137,29 @@ def test_domain_validation_on_host(lib, dom, expect):
     assert lib.psatd_last_error().decode()
 
 
+def test_plan_flags_match_the_header():
+    # every PSATD_FLAG_* of include/psatd.h has the binding's value, and the
+    # planner accepts each of them (fails only at the device query without a GPU)
+    import re
+    text = open(HEADER).read()
+    flags = dict(re.findall(r"#define PSATD_FLAG_(\w+) (0x[0-9a-f]+)u", text))
+    assert "RADIX4_LINES" in flags
+    for name, val in flags.items():
+        assert getattr(b, "FLAG_" + name) == int(val, 16), name
+
+
+@pytest.mark.parametrize("flag", ["RADIX4_LINES", "GENERIC_KERNELS"])
+def test_known_flags_pass_host_validation(lib, flag):
+    out = ctypes.c_void_p()
+    st = lib.psatd_plan(ctypes.byref(_cfg(flags=getattr(b, "FLAG_" + flag))), ctypes.byref(_desc()),
+                        1, 0, ctypes.byref(out))
+    assert st in (0, -4), lib.psatd_last_error().decode()
+    if st == 0:
+        lib.psatd_destroy(out)
+    st = lib.psatd_plan(ctypes.byref(_cfg(flags=0x80)), ctypes.byref(_desc()), 1, 0, ctypes.byref(out))
+    assert st == -1 and "flag" in lib.psatd_last_error().decode()
+
+
 @pytest.mark.parametrize("desc,cfg,expect", [
     (_desc(), _cfg(flags=b.FLAG_PSTD, source_mode=1), -1),   # PSTD takes J only
     (_desc(dt=0.7), _cfg(flags=b.FLAG_PSTD), -1),            # c dt |k|max / 2 = 1.18 > 1
