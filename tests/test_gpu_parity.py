@@ -119,6 +119,25 @@ def test_radix4_line_passes_batched():
     assert err < TOL["fp32"]
 
 
+# ----------------------------------------------------------------- fused modes per thread
+# An untuned plan takes the smallest compiled modes-per-thread count whose
+# workgroup holds the z lines: long z lines fall back to the larger counts.
+@pytest.mark.parametrize("index,shape,mpt", [
+    (1, (1024, 8), 2), (1, (2048, 8), 4), (1, (4096, 4), 8), (1, (1536, 6), 4),
+    (2, (1024, 2, 4), 2), (2, (2048, 2, 4), 4), (2, (1536, 4, 2), 4)])
+def test_fused_modes_per_thread_fallbacks(index, shape, mpt):
+    import paper_1608_05739_amd as pk
+    w = _w(index, shape, 2)
+    plan = pk.Plan(w.patches, precision="fp32", source_mode="rho", path="fused")
+    info = plan.info
+    plan.close()
+    assert f"mpt={mpt} " in info, info
+    say(f"fused fp32 {shape}: mpt={mpt}")
+    err = compare(run_gpu(w, "fp32", "fused", w.steps), run_oracle(w, "fp32", w.steps))
+    say(f"  rel L2 = {err:.3e}")
+    assert err < TOL["fp32"]
+
+
 # ----------------------------------------------------------------- batched patches
 def test_batched_patches_workload3_subset():
     w = fixtures.workload(3, npatches=24, steps=3)
