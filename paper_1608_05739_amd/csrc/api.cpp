@@ -309,12 +309,12 @@ void line_geometry(int kind, const PatchDev& P, int* nlines, int* L) {
   }
 }
 
-// Build a line pass over all patches for the given components.
 // Points per thread of the plan's generic line passes.
 int line_ppt(const psatd_plan_s* plan) {
   return (plan->cfg.flags & PSATD_FLAG_RADIX4_LINES) ? 4 : kMaxPts;
 }
 
+// Build a line pass over all patches for the given components.
 Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
                     std::vector<WorkItem>& items, int lines_override = 0) {
   const int ppt = line_ppt(plan);
@@ -745,32 +745,32 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     if (ps.type == kFused) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
     if (ps.type == kLine || ps.type == kFused) {
       for (int m : vars) {
-      if (e != hipSuccess) break;
-      for (int R : {1, 2, 4, 8, 16, 32}) {
-        std::vector<WorkItem> its;
-        Pass c;
-        if (ps.type == kLine) {
-          c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
-        } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
-          continue;
+        if (e != hipSuccess) break;
+        for (int R : {1, 2, 4, 8, 16, 32}) {
+          std::vector<WorkItem> its;
+          Pass c;
+          if (ps.type == kLine) {
+            c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
+          } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
+            continue;
+          }
+          bool seen = false;
+          for (const Cand& x : cands)
+            seen = seen || (x.pass.lines == c.lines && x.pass.mpt == c.mpt && x.pass.ppt == c.ppt);
+          if (seen) continue;
+          c.d_items = nullptr;
+          if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
+          WorkItem* d = nullptr;
+          e = hipMalloc(&d, sizeof(WorkItem) * its.size());
+          if (e == hipSuccess)
+            e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
+          if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            break;
+          }
+          c.d_items = d;
+          cands.push_back(Cand{c, d});
         }
-        bool seen = false;
-        for (const Cand& x : cands)
-          seen = seen || (x.pass.lines == c.lines && x.pass.mpt == c.mpt && x.pass.ppt == c.ppt);
-        if (seen) continue;
-        c.d_items = nullptr;
-        if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
-        WorkItem* d = nullptr;
-        e = hipMalloc(&d, sizeof(WorkItem) * its.size());
-        if (e == hipSuccess)
-          e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-          if (d) (void)hipFree(d);
-          break;
-        }
-        c.d_items = d;
-        cands.push_back(Cand{c, d});
-      }
       }
     }
     int best_c = 0, best_g = ps.shape.grid;
