@@ -486,7 +486,7 @@ def main():
 
     cfg = {"workload": w.name, "cells": cells, "patches": len(w.patches), "steps_per_config": default_steps,
            "source_form": mode, "storage": "f32", "arithmetic": "f64", "path": "fused",
-           "graph": True, "generic_line_radix": 4 if radix4 else 8}
+           "graph": True, "autotune": True, "radix4_lines": radix4}
     out = {
         "metric": METRIC,
         "value": value,
