@@ -368,7 +368,7 @@ Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& 
 // choice takes z lines the smaller one cannot hold.
 std::vector<int> fused_mpt_choices(int precision, int ndim) {
   if (precision == PSATD_FP32) return ndim == 2 ? std::vector<int>{2, 4, 8} : std::vector<int>{2, 4};
-  return {ndim == 2 ? 4 : 2};
+  return ndim == 2 ? std::vector<int>{2, 4} : std::vector<int>{2};
 }
 
 psatd_status make_fused_pass_mpt(const psatd_plan_s* plan, std::vector<WorkItem>& items, Pass* out,

@@ -593,7 +593,7 @@ hipError_t launch_line_pass(int kind, int precision, int ppt, const LaunchShape&
 bool fused_supported(int precision, int ndim, int mpt) {
   if (precision == 0)
     return (ndim == 2 && (mpt == 2 || mpt == 4 || mpt == 8)) || (ndim == 3 && (mpt == 2 || mpt == 4));
-  return (ndim == 2 && mpt == 4) || (ndim == 3 && mpt == 2);
+  return (ndim == 2 && (mpt == 2 || mpt == 4)) || (ndim == 3 && mpt == 2);
 }
 
 template <typename S, int DIM, int MPT>
@@ -638,8 +638,10 @@ hipError_t launch_fused_z(int precision, int ndim, int src, int mpt, const Launc
                     : fused_dispatch<float, 3, 4>(src, sh, stream, patches, items, nitems, w, ph);
   }
   if (ndim == 2)
-    return fused_dispatch<double, 2, 4>(src, sh, stream, patches, items, nitems,
-                                        static_cast<double*>(ws), ph);
+    return mpt == 2 ? fused_dispatch<double, 2, 2>(src, sh, stream, patches, items, nitems,
+                                                   static_cast<double*>(ws), ph)
+                    : fused_dispatch<double, 2, 4>(src, sh, stream, patches, items, nitems,
+                                                   static_cast<double*>(ws), ph);
   return fused_dispatch<double, 3, 2>(src, sh, stream, patches, items, nitems,
                                       static_cast<double*>(ws), ph);
 }
@@ -742,6 +744,7 @@ hipError_t configure_kernel_attributes() {
   if ((r = set_fused_attrs<float, 2, 8>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 3, 2>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<float, 3, 4>()) != hipSuccess) e = r;
+  if ((r = set_fused_attrs<double, 2, 2>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 3, 2>()) != hipSuccess) e = r;
   return e;
