@@ -123,22 +123,58 @@ def laser_2d(nx, nz, dx, dz, *, angle_deg, waist, tau, nharm, rng, amplitude=1.0
 
 
 def laser_3d(nx, ny, nz, d, *, angle_deg, waist, tau, nharm, rng, amplitude=1.0):
-    """3D version of :func:`laser_2d`: Gaussian beam in the (x, z) plane at angle_deg."""
+    """3D version of :func:`laser_2d`: Gaussian beam in the (x, z) plane at angle_deg.
+
+    The pulse s(x, y, z) = A(x, z) g(y) separates: the phase coordinate xi and
+    the in-plane transverse offset do not depend on y, and the envelope factor
+    exp(-r_perp^2/w^2) splits into exp(-(in-plane offset)^2/w^2) exp(-y^2/w^2).
+    Its spectrum is therefore one 2D transform times one 1D transform, and the
+    transverse projections of e_hat s and b_hat s (both constant directions
+    times s) share it: one inverse transform per output component.
+    """
     a = np.deg2rad(angle_deg)
     x = (np.arange(nx) - nx / 2) * d[0]
     y = (np.arange(ny) - ny / 2) * d[1]
     z = (np.arange(nz) - nz / 2) * d[2]
-    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    Z, X = np.meshgrid(z, x, indexing="ij")
     xi = X * np.cos(a) + Z * np.sin(a)
-    rp2 = (-X * np.sin(a) + Z * np.cos(a)) ** 2 + Y ** 2
-    env = np.exp(-rp2 / waist ** 2) * np.exp(-(xi / (C_LIGHT * tau)) ** 2)
-    s = amplitude * env * _harmonic_comb(xi, nharm, rng)
+    rp = -X * np.sin(a) + Z * np.cos(a)
+    A = amplitude * np.exp(-(rp / waist) ** 2) * np.exp(-(xi / (C_LIGHT * tau)) ** 2) \
+        * _harmonic_comb(xi, nharm, rng)
+    g = np.exp(-(y / waist) ** 2)
     khat = np.array([np.cos(a), 0.0, np.sin(a)])
     ehat = np.array([-np.sin(a), 0.0, np.cos(a)])
     bhat = np.cross(khat, ehat) / C_LIGHT
-    E = project_transverse([ehat[i] * s for i in range(3)], d)
-    B = project_transverse([bhat[i] * s for i in range(3)], d)
-    return E, B
+    # half spectrum of s: rfft over x of A, full transforms over z (of A) and y (of g)
+    Ah = sfft.fft(sfft.rfft(A, axis=1, workers=_WORKERS), axis=0, workers=_WORKERS)
+    gh = sfft.fft(g)
+    return _project_separable((Ah, gh), (nz, ny, nx), d, (ehat, bhat))
+
+
+def _project_separable(spec, shape, d, directions):
+    """Transverse parts of v s for constant vectors v, with s given by its
+    half spectrum s^(kz, ky, kx) = Ah(kz, kx) gh(ky) (r2c along x):
+    F^_i = v_i s^ - k_i (k.v) s^ / |k|^2 (the mean is kept)."""
+    Ah, gh = spec
+    nz, ny, nx = shape
+    KX = lattice_k(nx, d[0])[: nx // 2 + 1][None, None, :]
+    KY = lattice_k(ny, d[1])[None, :, None]
+    KZ = lattice_k(nz, d[2])[:, None, None]
+    sh = Ah[:, None, :] * gh[None, :, None]
+    k2 = KX * KX + KY * KY + KZ * KZ
+    inv = np.zeros_like(k2)
+    np.divide(1.0, k2, out=inv, where=k2 > 0)
+    del k2
+    out = []
+    for v in directions:
+        kv = (KX * v[0] + KY * v[1] + KZ * v[2]) * inv
+        comps = []
+        for i, ki in enumerate((KX, KY, KZ)):
+            f = sh * (v[i] - ki * kv)
+            comps.append(sfft.irfftn(f, s=shape, workers=_WORKERS))
+            del f
+        out.append(comps)
+    return tuple(out)
 
 
 def plane_wave_packets_3d(shape, d, *, nharm, max_angle_deg, rng):
@@ -210,7 +246,7 @@ def current_profile(shape, d, *, width, nmodes, min_wavelength, rng):
     y = np.arange(ny) * d[1]
     mz_max = max(1, int(np.floor(Lz / min_wavelength)))
     my_max = max(0, int(np.floor(Ly / min_wavelength))) if len(shape) == 3 else 0
-    P = []
+    Qs = []
     for _c in range(3):
         Q = np.zeros((nz, ny))
         for _m in range(nmodes):
@@ -219,12 +255,23 @@ def current_profile(shape, d, *, width, nmodes, min_wavelength, rng):
             amp = rng.normal() / np.sqrt(nmodes)
             ph = rng.uniform(0.0, 2.0 * np.pi)
             Q += amp * np.cos(2.0 * np.pi * (mz * z[:, None] / Lz + my * y[None, :] / Ly) + ph)
-        if len(shape) == 2:
-            P.append(Q[:, 0][:, None] * G[None, :])
-        else:
-            P.append(Q[:, :, None] * G[None, None, :])
-    grads = [spectral_grad(P[c], d) for c in range(3)]
-    D = [grads[c][c] for c in range(3)]
+        Qs.append(Q)
+
+    def outer(q, g):
+        return q[:, 0][:, None] * g[None, :] if len(shape) == 2 else q[:, :, None] * g[None, None, :]
+
+    def deriv(f, axis, n, dd):
+        # spectral derivative along one axis (lattice k, Nyquist -> 0)
+        k = lattice_k(n, dd).reshape([-1 if a == axis else 1 for a in range(f.ndim)])
+        return np.real(sfft.ifft(1j * k * sfft.fft(f, axis=axis), axis=axis))
+
+    # P_c = Q_c(z, y) G(x) is separable, so its spectral derivative along one
+    # axis is the 1D (or 2D) derivative of the factor that depends on it
+    P = [outer(Qs[c], G) for c in range(3)]
+    Gx = deriv(G, 0, nx, d[0])
+    D = [outer(Qs[0], Gx),
+         outer(deriv(Qs[1], 1, ny, d[1]), G) if len(shape) == 3 else np.zeros(shape),
+         outer(deriv(Qs[2], 0, nz, d[2]), G)]
     return P, D
 
 

@@ -107,9 +107,67 @@ def run_oracle(w, precision, steps, form="rho", order=0, patches=None, E0=None, 
     return outE, outB
 
 
-def compare(gpu, ref):
-    """Relative L2 of (E, B) over all patches and components."""
+COMPONENTS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+
+
+def component_errors(got, ref):
+    """Per-component errors of one patch: got, ref = six arrays (E then B).
+
+    For a component whose reference is not identically zero: the relative L2
+    error against that component's own norm, and the largest pointwise error
+    over that component's own largest value.  For an identically zero
+    reference: the output's norm over the norm of all six reference
+    components (it must stay at rounding).  Returns {name: (rel_l2, max_rel)}.
+    """
+    total = np.sqrt(sum(float(np.sum(np.asarray(r, np.float64) ** 2)) for r in ref))
+    out = {}
+    for name, g, r in zip(COMPONENTS, got, ref):
+        g = np.asarray(g, np.float64)
+        r = np.asarray(r, np.float64)
+        nr = float(np.sqrt(np.sum(r * r)))
+        if nr == 0.0:
+            e = float(np.sqrt(np.sum(g * g))) / max(total, 1e-300)
+            out[name] = (e, e)
+        else:
+            d = g - r
+            out[name] = (float(np.sqrt(np.sum(d * d))) / nr,
+                         float(np.max(np.abs(d))) / float(np.max(np.abs(r))))
+    return out
+
+
+def compare(gpu, ref, label=None):
+    """Worst error over every patch and every component of (E, B).
+
+    Each component of each patch is measured against its own scale
+    (``component_errors``): the relative L2 error and the largest pointwise
+    error relative to the component's largest value; a component whose
+    reference is identically zero is measured against the patch's field norm.
+    Returns the largest of all these, so that a wrong low-amplitude component
+    cannot hide behind the others.  Prints the per-component worst values.
+    """
+    (gE, gB), (rE, rB) = gpu, ref
+    worst = {c: (0.0, 0.0, -1) for c in COMPONENTS}
+    for p, (ge, gb, re_, rb) in enumerate(zip(gE, gB, rE, rB)):
+        for name, (e2, em) in component_errors(list(ge) + list(gb), list(re_) + list(rb)).items():
+            w2, wm, _ = worst[name]
+            if max(e2, em) > max(w2, wm):
+                worst[name] = (e2, em, p)
+            else:
+                worst[name] = (max(w2, e2), max(wm, em), worst[name][2])
+    text = ", ".join(f"{c} {v[0]:.2e}/{v[1]:.2e}" for c, v in worst.items())
+    say(f"  {label + ': ' if label else ''}per component rel L2 / max rel: {text}")
+    return max(max(v[0], v[1]) for v in worst.values())
+
+
+def compare_global(gpu, ref):
+    """Relative L2 of (E, B) pooled over all patches and components (reported
+    beside ``compare``, never asserted alone)."""
     (gE, gB), (rE, rB) = gpu, ref
     a = [x for pe, pb in zip(gE, gB) for x in pe + pb]
     b = [x for pe, pb in zip(rE, rB) for x in pe + pb]
     return rel_l2(a, b)
+
+
+def field_error(got, ref, label=None):
+    """``compare`` for one patch given as six arrays (Ex, Ey, Ez, Bx, By, Bz)."""
+    return compare(([list(got[:3])], [list(got[3:])]), ([list(ref[:3])], [list(ref[3:])]), label)

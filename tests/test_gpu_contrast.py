@@ -12,7 +12,7 @@ import pytest
 
 import fixtures
 import paper_1608_05739_amd as pk
-from gpu_support import rel_l2, rounded, say
+from gpu_support import field_error, rounded, say
 from oracle import contrast as C
 from oracle import dispersion as D
 
@@ -94,7 +94,7 @@ def test_fdtd_matches_oracle(scheme, order, index, shape, frac, precision, sourc
     say(f"fdtd {scheme} p={order} {shape} dt={frac}dx {precision} sources={sources}")
     got = _gpu_fdtd(scheme, order, p, E0, B0, sched, steps, precision)
     ref = _oracle_fdtd(scheme, order, p, E0, B0, sched, steps, precision)
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"  rel L2 = {err:.3e}")
     assert err < TOL[precision]
 
@@ -119,7 +119,7 @@ def test_fdtd_offset_and_neighbours_untouched():
         h = t.cpu().numpy()
         assert np.all(h[:off] == -3.25) and np.all(h[off + p.cells:] == -3.25)
         got.append(h[off:off + p.cells].reshape(p.shape))
-    assert rel_l2(got, ref) < 1e-12
+    assert field_error(got, ref) < 1e-12
 
 
 def _gpu_pstd(p, E0, B0, sched, steps, precision, path, order=0):
@@ -169,7 +169,7 @@ def test_pstd_matches_oracle(index, shape, frac, precision, path, order, sources
     say(f"pstd {shape} dt={frac}dx {precision} {path} p={order} sources={sources}")
     got = _gpu_pstd(p, E0, B0, sched, steps, precision, path, order)
     ref = _oracle_pstd(p, E0, B0, sched, steps, precision, order)
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"  rel L2 = {err:.3e}")
     assert err < TOL[precision]
 
@@ -226,7 +226,7 @@ def test_fdtd_fullsize_4096_fp32_vs_oracle(scheme, frac):
     say(f"fdtd {scheme} full size {p.shape} fp32, 2 steps")
     got = _gpu_fdtd(scheme, 2, p, E0, B0, sched, 2, "fp32")
     ref = _oracle_fdtd(scheme, 2, p, E0, B0, sched, 2, "fp32")
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"  rel L2 = {err:.3e}")
     assert err < 1e-5
 
@@ -236,6 +236,6 @@ def test_pstd_fullsize_4096_fp32_vs_oracle():
     say(f"pstd full size {p.shape} fp32 fused, 1 step")
     got = _gpu_pstd(p, E0, B0, sched, 1, "fp32", "fused")
     ref = _oracle_pstd(p, E0, B0, sched, 1, "fp32")
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"  rel L2 = {err:.3e}")
     assert err < 1e-5

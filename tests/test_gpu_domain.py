@@ -9,7 +9,7 @@ import pytest
 
 import fixtures
 import paper_1608_05739_amd as pk
-from gpu_support import rel_l2, rounded, say
+from gpu_support import field_error, rel_l2, rounded, say
 from oracle.decomposition import decomposed_step
 
 pytestmark = pytest.mark.gpu
@@ -75,7 +75,7 @@ def test_domain_2d_matches_oracle_decomposition(precision, sources):
     got = _run_domain(w.E0[0], w.B0[0], p, parts, guard, 3, precision,
                       source="rho" if sources else "vacuum", schedule=sched)
     ref = _run_oracle(w.E0[0], w.B0[0], p, parts, guard, 3, precision, schedule=sched)
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"  rel L2 = {err:.3e}")
     assert err < TOL[precision]
 
@@ -89,7 +89,7 @@ def test_domain_3d_matches_oracle_decomposition():
     got = _run_domain(w.E0[0], w.B0[0], p, parts, guard, 2, "fp64", source="rho",
                       schedule=w.schedule[0])
     ref = _run_oracle(w.E0[0], w.B0[0], p, parts, guard, 2, "fp64", schedule=w.schedule[0])
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"  rel L2 = {err:.3e}")
     assert err < TOL["fp64"]
 
@@ -120,7 +120,7 @@ def test_enough_guards_reproduce_the_global_step_for_centered_order_p():
     ref = _global_gpu(E0, B0, p, 4, 8, True)
     # boxes of 64, guards 40: 144-wide patches
     got = _run_domain(E0, B0, p, (2, 1, 2), (40, 0, 40), 4, "fp64")
-    err = rel_l2(got, ref)
+    err = field_error(got, ref)
     say(f"centered p = 8, guard 40: decomposed vs global rel L2 = {err:.3e}")
     assert err < 1e-12
 

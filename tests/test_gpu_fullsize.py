@@ -8,7 +8,7 @@ import pytest
 import fixtures
 import oracle
 import paper_1608_05739_amd as pk
-from gpu_support import rel_l2, say
+from gpu_support import field_error, say
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +55,7 @@ def test_fullsize_one_step_vs_oracle(w1):
     J, ro, rn = w1.schedule[0].sources(0, dtype=np.float32)
     En, Bn = oracle.psatd_step(E, B, [x.astype(np.float64) for x in J], ro.astype(np.float64),
                                rn.astype(np.float64), d=p.d, dt=p.dt)
-    err = rel_l2(got, En + Bn)
+    err = field_error(got, En + Bn)
     say(f"  rel L2 = {err:.3e}")
     assert err < 1e-5
 
@@ -73,7 +73,7 @@ def test_fullsize_order_p_one_step_vs_oracle(w1, order, centered):
     En, Bn = oracle.psatd_step(E, B, [x.astype(np.float64) for x in J], ro.astype(np.float64),
                                rn.astype(np.float64), d=p.d, dt=p.dt, order=order,
                                stencil="centered" if centered else "staggered")
-    err = rel_l2(got, En + Bn)
+    err = field_error(got, En + Bn)
     say(f"  rel L2 = {err:.3e}")
     assert err < 1e-5
 
@@ -83,7 +83,7 @@ def test_fast_path_matches_generic_kernels(w1):
     a, _ = _run(w1, 3, generic=False)
     b, names = _run(w1, 3, generic=True)
     assert names == ["x_r2c_fwd", "z_fused", "x_c2r_inv"]
-    err = rel_l2(a, b)
+    err = field_error(a, b)
     say(f"  rel L2 (fast vs generic) = {err:.3e}")
     assert err < 2e-6
 
@@ -121,7 +121,7 @@ def test_fullsize_1000_steps_vacuum_vs_one_oracle_step(w1):
     plan.close()
     E0, B0 = _oracle_inputs(w1)
     En, Bn = oracle.psatd_step(E0, B0, d=p.d, dt=K * p.dt)
-    err = rel_l2(got, En + Bn)
+    err = field_error(got, En + Bn)
     say(f"  rel L2 after {K} steps = {err:.3e}")
     assert err < 1e-5
 
@@ -156,6 +156,81 @@ def test_fullsize_1000_steps_sources_vs_one_oracle_step(w1):
     Jo = [a.astype(np.float64) for a in J32]
     rho_new = -K * p.dt * divJ32.astype(np.float64)
     En, Bn = oracle.psatd_step(E0, B0, Jo, np.zeros_like(rho_new), rho_new, d=p.d, dt=K * p.dt)
-    err = rel_l2(got, En + Bn)
+    err = field_error(got, En + Bn)
     say(f"  rel L2 after {K} steps = {err:.3e}")
     assert err < 1e-5
+
+
+# ----------------------------------------------------------------- FP64 plain at full size
+def test_fullsize_fp64_plain_one_step_vs_oracle(w1):
+    """The plain FP64 path at 4096 x 4096 with sources: one step against the
+    oracle on the same FP64 inputs, at the FP64 target (1e-12)."""
+    p = w1.patches[0]
+    say("fp64 plain, 1 step at 4096x4096 with sources vs oracle")
+    import torch
+    plan = pk.Plan([p], precision="fp64", source_mode="rho", path="plain")
+    E = [_dev(a, np.float64) for a in w1.E0[0]]
+    B = [_dev(a, np.float64) for a in w1.B0[0]]
+    J, ro, rn = w1.schedule[0].sources(0, dtype=np.float64)
+    plan.push(E, B, [_dev(x, np.float64) for x in J], _dev(ro, np.float64), _dev(rn, np.float64),
+              steps=1)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    En, Bn = oracle.psatd_step(list(w1.E0[0]), list(w1.B0[0]), J, ro, rn, d=p.d, dt=p.dt)
+    err = field_error(got, En + Bn)
+    assert err < 1e-12
+
+
+def test_fullsize_fp64_plain_1000_steps_vs_one_oracle_step(w1):
+    """1000 plain FP64 vacuum steps at 4096 x 4096 against one oracle step of
+    1000 dt (semigroup of the exact per-mode flow), at 1e-12."""
+    import torch
+    p = w1.patches[0]
+    K = 1000
+    say(f"fp64 plain vacuum, {K} steps at 4096x4096 vs one oracle step of {K} dt")
+    plan = pk.Plan([p], precision="fp64", source_mode="vacuum", path="plain", graph=True)
+    E = [_dev(a, np.float64) for a in w1.E0[0]]
+    B = [_dev(a, np.float64) for a in w1.B0[0]]
+    plan.push(E, B, steps=K)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    En, Bn = oracle.psatd_step(list(w1.E0[0]), list(w1.B0[0]), d=p.d, dt=K * p.dt)
+    err = field_error(got, En + Bn)
+    assert err < 1e-12
+
+
+# ----------------------------------------------------------------- no Courant condition
+@pytest.mark.parametrize("cdt", [5.0, 20.0])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fullsize_large_time_step_vs_oracle(w1, cdt, precision):
+    """PSATD has no Courant condition (Table 1, PSATD row): at c dt = 5 dx and
+    20 dx (theta up to ~90 rad at the grid corner, deep in the argument
+    reduction of the kernels' sincos) one step with sources at 4096 x 4096
+    still matches the oracle (FP32: the specialized kernels; FP64: plain)."""
+    import torch
+    p0 = w1.patches[0]
+    dt = cdt * p0.dx
+    p = fixtures.workloads.Patch(2, p0.nx, 1, p0.nz, p0.dx, p0.dy, p0.dz, dt)
+    s = w1.schedule[0]
+    sched = fixtures.SourceSchedule(s.P, s.D, s.phases, dt)
+    dtype = np.float32 if precision == "fp32" else np.float64
+    say(f"{precision}, c dt = {cdt} dx, 1 step at 4096x4096 with sources vs oracle")
+    plan = pk.Plan([p], precision=precision, source_mode="rho",
+                   path="fused" if precision == "fp32" else "plain")
+    if precision == "fp32":
+        assert plan.pass_names == ["x_r2c_fwd", "z_fused", "x_c2r_inv"]
+    E = [_dev(a, dtype) for a in w1.E0[0]]
+    B = [_dev(a, dtype) for a in w1.B0[0]]
+    J, ro, rn = sched.sources(3, dtype=dtype)
+    plan.push(E, B, [_dev(x, dtype) for x in J], _dev(ro, dtype), _dev(rn, dtype), steps=1)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    E0 = [np.asarray(a, dtype).astype(np.float64) for a in w1.E0[0]]
+    B0 = [np.asarray(a, dtype).astype(np.float64) for a in w1.B0[0]]
+    En, Bn = oracle.psatd_step(E0, B0, [x.astype(np.float64) for x in J], ro.astype(np.float64),
+                               rn.astype(np.float64), d=p.d, dt=dt)
+    err = field_error(got, En + Bn)
+    assert err < (1e-5 if precision == "fp32" else 1e-12)

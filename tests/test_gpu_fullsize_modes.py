@@ -1,35 +1,35 @@
-"""GPU parity at the full sizes of the 3D and batched workloads.
+"""GPU parity at the full sizes of the 3D and batched workloads, at each
+workload's stated step count.
 
-The 3D grids (512^3 and 1024 x 1024 x 512) are too large for the FP64
-oracle to transform whole in a test, so their inputs are a seeded
-superposition of a few lattice Fourier modes: each mode evolves on its own,
-the oracle's update (``oracle.update_modes``) gives its exact spectrum after
-K steps, and the result is synthesized at 2^20 sampled grid points and
-compared with the GPU output there.  The modes include a generic and
-near-Nyquist wavevectors, an x-Nyquist mode (the r2c packing of the Nyquist
-column), a pure z-Nyquist mode and the DC mode (both k = 0), with transverse
-E and B, currents with a longitudinal part, and rho from exact discrete
-continuity.  The batched workload (256 patches) runs whole against the
-oracle, patch by patch.
+3D (512^3 for 200 steps, 1024 x 1024 x 512 for 100 steps).  The FP64 oracle
+cannot transform these grids whole inside a test, so the inputs are a seeded
+superposition of lattice Fourier modes: one mode in every kx column
+(0 .. nx/2, the x-Nyquist column included, which the r2c packing stores
+apart), plus many modes at random (kx, ky, kz), plus the DC mode and modes on
+the y and z Nyquist planes.  Every x line, y line and z line of the grid then
+carries signal.  Each mode evolves on its own: ``oracle.update_modes`` advances
+its amplitudes step by step (with sources: J constant, rho^n = n drho from
+exact discrete continuity), and the exact field after K steps is synthesized
+on whole planes (z = const, y = const and x = const) by a 2D inverse FFT of
+the plane's spectrum in FP64.  The GPU output is compared there, component by
+component.
+
+Batched (256 patches, 500 steps).  All patches run in one plan for the
+stated 500 vacuum steps; each patch is compared with one oracle step of
+500 dt (the update is the exact flow of each mode, so K steps of dt equal one
+step of K dt; the oracle's semigroup pin covers that identity).
 """
 
 import numpy as np
 import pytest
+import scipy.fft as sfft
 
 import fixtures
 import oracle
 import paper_1608_05739_amd as pk
-from gpu_support import rel_l2, say
+from gpu_support import compare, say
 
 pytestmark = pytest.mark.gpu
-
-NSAMPLE = 1 << 20
-
-
-def _modes(shape, rng):
-    nz, ny, nx = shape
-    return [(5, 3, -7), (nx // 2 - 1, 1, 2), (1, -(ny // 2 - 3), nz // 2 - 2),
-            (nx // 2, 4, 3), (0, 0, nz // 2), (0, 0, 0), (17, -11, 29)]
 
 
 def _keff(m, n, d):
@@ -42,131 +42,158 @@ def _keff(m, n, d):
     return 2.0 * np.pi * mm / (n * d)
 
 
-def _setup(shape, d, dt, sources, rng):
+def _mode_list(shape, rng, extra):
     nz, ny, nx = shape
-    modes = []
-    for m in _modes(shape, rng):
-        k = np.array([_keff(m[0], nx, d[0]), _keff(m[1], ny, d[1]), _keff(m[2], nz, d[2])])
-        kn = np.linalg.norm(k)
-
-        def transverse():
-            v = rng.normal(size=3) + 1j * rng.normal(size=3)
-            if kn > 0:
-                kh = k / kn
-                v = v - kh * (kh @ v)
-            return 0.5 * v
-
-        E = transverse()
-        B = transverse()
-        J = (0.3 * (rng.normal(size=3) + 1j * rng.normal(size=3))) if sources else np.zeros(3, complex)
-        modes.append({"m": m, "k": k, "E": E, "B": B, "J": J,
-                      # d rho / dt = -i k.J  (exact discrete continuity), rho^0 = 0
-                      "drho": -dt * 1j * (k @ J)})
-    return modes
+    m = []
+    for mx in range(nx // 2 + 1):  # every kx column of the r2c spectrum
+        m.append((mx, int(rng.integers(-ny // 2, ny // 2)), int(rng.integers(-nz // 2, nz // 2))))
+    for _ in range(extra):
+        m.append((int(rng.integers(-nx // 2, nx // 2)), int(rng.integers(-ny // 2, ny // 2)),
+                  int(rng.integers(-nz // 2, nz // 2))))
+    m += [(0, 0, 0), (0, ny // 2, 3), (5, -7, nz // 2), (nx // 2, ny // 2, nz // 2), (1, 0, 0),
+          (0, 0, nz // 2 - 1), (0, ny // 2 - 1, 0)]
+    return np.array(m, dtype=np.int64)
 
 
-def _exact(modes, K, dt, sources):
-    """Spectral amplitudes after K steps (J constant, rho^n = n drho)."""
-    out = []
-    for md in modes:
-        E = [np.array([md["E"][i]]) for i in range(3)]
-        B = [np.array([md["B"][i]]) for i in range(3)]
-        k = tuple(np.array([md["k"][i]]) for i in range(3))
-        for n in range(K):
-            if sources:
-                J = [np.array([md["J"][i]]) for i in range(3)]
-                E, B = oracle.update_modes(E, B, k, dt, Jk=J, rho_old_k=np.array([n * md["drho"]]),
-                                           rho_new_k=np.array([(n + 1) * md["drho"]]))
-            else:
-                E, B = oracle.update_modes(E, B, k, dt)
-        out.append((np.array([e[0] for e in E]), np.array([b[0] for b in B])))
-    return out
-
-
-def _phase_factors(torch, m, shape):
-    """exp(2 pi i m_a i_a / n_a) per axis, exact integer phases, complex128 on the GPU."""
+def _setup(shape, d, dt, sources, rng, extra):
     nz, ny, nx = shape
-    f = []
-    for mi, n in ((m[2], nz), (m[1], ny), (m[0], nx)):
-        i = torch.arange(n, device="cuda:0", dtype=torch.int64)
-        ph = ((mi * i) % n).to(torch.float64) * (2.0 * np.pi / n)
-        f.append(torch.polar(torch.ones_like(ph), ph))
-    return f[0][:, None, None], f[1][None, :, None], f[2][None, None, :]
+    m = _mode_list(shape, rng, extra)
+    M = len(m)
+    k = np.array([[_keff(a, nx, d[0]), _keff(b, ny, d[1]), _keff(c, nz, d[2])] for a, b, c in m])
+    kn = np.linalg.norm(k, axis=1)
+    kh = np.divide(k, kn[:, None], out=np.zeros_like(k), where=kn[:, None] > 0)
+
+    def transverse():
+        v = rng.normal(size=(M, 3)) + 1j * rng.normal(size=(M, 3))
+        v -= kh * np.sum(kh * v, axis=1)[:, None]
+        return 0.5 * v / np.sqrt(M)
+
+    E = transverse()
+    B = transverse()
+    J = (0.3 * (rng.normal(size=(M, 3)) + 1j * rng.normal(size=(M, 3))) / np.sqrt(M)
+         if sources else np.zeros((M, 3), complex))
+    drho = -dt * 1j * np.sum(k * J, axis=1)  # d rho / dt = -i k.J (exact continuity), rho^0 = 0
+    return {"m": m, "k": k, "E": E, "B": B, "J": J, "drho": drho}
 
 
-def _field(torch, shape, modes, amp):
-    """sum_m 2 Re(amp(m) exp(i theta_m(x))) as a flat FP32 device tensor."""
-    acc = torch.zeros(shape, dtype=torch.float64, device="cuda:0")
-    for md in modes:
-        a = complex(amp(md))
-        if a == 0:
-            continue
-        fz, fy, fx = _phase_factors(torch, md["m"], shape)
-        acc += 2.0 * torch.real(a * (fz * fy * fx))
-    return acc.to(torch.float32).reshape(-1)
+def _exact(md, K, dt, sources):
+    """Amplitudes of every mode after K steps of the oracle's update."""
+    k = tuple(md["k"][:, i] for i in range(3))
+    E = [md["E"][:, i].copy() for i in range(3)]
+    B = [md["B"][:, i].copy() for i in range(3)]
+    J = [md["J"][:, i] for i in range(3)]
+    for n in range(K):
+        if sources:
+            E, B = oracle.update_modes(E, B, k, dt, Jk=J, rho_old_k=n * md["drho"],
+                                       rho_new_k=(n + 1) * md["drho"])
+        else:
+            E, B = oracle.update_modes(E, B, k, dt)
+    return np.stack(E + B, axis=1)  # (M, 6)
 
 
-def _synth(modes, amps, comp, idx, shape):
+def _device_field(torch, shape, m, amp, device="cuda:0"):
+    """sum_modes 2 Re(amp exp(i 2 pi m.x / n)) as a flat FP32 device tensor.
+
+    The modes are scattered into a half spectrum (conjugate partners of the
+    kx = 0 and kx = nx/2 planes included) and transformed by one FP64 inverse
+    FFT; an error there can only make the test fail, since the expected
+    values below are synthesized independently on the host."""
     nz, ny, nx = shape
-    iz, rem = np.divmod(idx, ny * nx)
-    iy, ix = np.divmod(rem, nx)
-    val = np.zeros(idx.size)
-    for md, a in zip(modes, amps):
-        m = md["m"]
-        th = 2 * np.pi * (((m[0] * ix) % nx) / nx + ((m[1] * iy) % ny) / ny + ((m[2] * iz) % nz) / nz)
-        val += 2.0 * np.real(a[comp] * np.exp(1j * th))
-    return val
+    S = torch.zeros((nz, ny, nx // 2 + 1), dtype=torch.complex128, device=device)
+    mx, my, mz = m[:, 0] % nx, m[:, 1] % ny, m[:, 2] % nz
+    a = np.asarray(amp, np.complex128)
+    # a mode with kx index above nx/2 is the conjugate of (-m): store it there
+    flip = mx > nx // 2
+    ix = np.where(flip, (nx - mx) % nx, mx)
+    iy = np.where(flip, (-my) % ny, my)
+    iz = np.where(flip, (-mz) % nz, mz)
+    av = np.where(flip, np.conj(a), a)
+    # the inverse r2c transform of a value v at 0 < kx < nx/2 yields
+    # 2 Re(v e) / N (its conjugate partner is implied); on the kx = 0 and
+    # kx = nx/2 planes it keeps only the real part, so there the partner
+    # conj(v) at (-kz, -ky) is stored explicitly
+    self_conj = (ix == 0) | (ix == nx // 2)
+    idx = [torch.from_numpy(v).to(device) for v in (iz, iy, ix)]
+    vals = torch.from_numpy(av).to(device)
+    S.index_put_(tuple(idx), vals, accumulate=True)
+    if np.any(self_conj):
+        sel = np.nonzero(self_conj)[0]
+        cidx = [torch.from_numpy(v).to(device) for v in ((-iz[sel]) % nz, (-iy[sel]) % ny, ix[sel])]
+        S.index_put_(tuple(cidx), torch.from_numpy(np.conj(av[sel])).to(device), accumulate=True)
+    f = torch.fft.irfftn(S, s=(nz, ny, nx)) * float(nx * ny * nz)
+    return f.to(torch.float32).reshape(-1)
+
+
+def _plane(m, amp, shape, axis, pos):
+    """Exact field sum_modes 2 Re(amp exp(i theta)) on the plane {axis = pos}
+    (axis 0: z, 1: y, 2: x), by a 2D inverse FFT of the plane's spectrum."""
+    nz, ny, nx = shape
+    n = (nz, ny, nx)
+    mi = (m[:, 2], m[:, 1], m[:, 0])  # indices in [z, y, x] order
+    keep = [a for a in range(3) if a != axis]
+    ph = np.exp(2j * np.pi * ((mi[axis] * pos) % n[axis]) / n[axis])
+    S = np.zeros((n[keep[0]], n[keep[1]]), complex)
+    np.add.at(S, (mi[keep[0]] % n[keep[0]], mi[keep[1]] % n[keep[1]]), amp * ph)
+    return 2.0 * np.real(sfft.ifft2(S, workers=-1)) * (n[keep[0]] * n[keep[1]])
+
+
+def _gpu_plane(t, shape, axis, pos):
+    v = t.view(shape)
+    s = v[pos] if axis == 0 else (v[:, pos] if axis == 1 else v[:, :, pos])
+    return s.double().cpu().numpy()
 
 
 @pytest.mark.parametrize("index,sources", [(2, False), (2, True), (4, False), (4, True)])
-def test_fullsize_3d_lattice_modes(index, sources):
+def test_fullsize_3d_dense_modes_stated_steps(index, sources):
     import torch
     w = fixtures.workload(index, build_fields=False)
     p = w.patches[0]
     shape = p.shape
-    K = 3
+    K = w.steps  # 200 (512^3) or 100 (1024 x 1024 x 512)
     rng = np.random.default_rng(5000 + 10 * index + int(sources))
-    say(f"workload {index} full size {shape}, {'rho form' if sources else 'vacuum'}, {K} steps")
-    modes = _setup(shape, p.d, p.dt, sources, rng)
-    E = [_field(torch, shape, modes, lambda md, i=i: md["E"][i]) for i in range(3)]
-    B = [_field(torch, shape, modes, lambda md, i=i: md["B"][i]) for i in range(3)]
+    md = _setup(shape, p.d, p.dt, sources, rng, extra=1024)
+    say(f"workload {index} full size {shape}, {'rho form' if sources else 'vacuum'}, "
+        f"{K} steps, {len(md['m'])} modes")
+    E = [_device_field(torch, shape, md["m"], md["E"][:, i]) for i in range(3)]
+    B = [_device_field(torch, shape, md["m"], md["B"][:, i]) for i in range(3)]
     mode = "rho" if sources else "vacuum"
-    plan = pk.Plan([p], precision="fp32", source_mode=mode, path="fused")
+    plan = pk.Plan([p], precision="fp32", source_mode=mode, path="fused", graph=not sources)
     if sources:
-        J = [_field(torch, shape, modes, lambda md, i=i: md["J"][i]) for i in range(3)]
-        drho = _field(torch, shape, modes, lambda md: md["drho"]).to(torch.float64)
+        J = [_device_field(torch, shape, md["m"], md["J"][:, i]) for i in range(3)]
+        drho = _device_field(torch, shape, md["m"], md["drho"]).to(torch.float64)
         ro = torch.empty(drho.shape, dtype=torch.float32, device="cuda:0")
         rn = torch.empty_like(ro)
         for n in range(K):
-            ro.copy_(drho * n)
-            rn.copy_(drho * (n + 1))
+            torch.mul(drho, float(n), out=ro)
+            torch.mul(drho, float(n + 1), out=rn)
             plan.push(E, B, J, ro, rn, steps=1)
     else:
         plan.push(E, B, steps=K)
     torch.cuda.synchronize()
     plan.close()
-    exact = _exact(modes, K, p.dt, sources)
-    idx = np.sort(rng.choice(p.cells, size=NSAMPLE, replace=False))
-    tidx = torch.from_numpy(idx).to("cuda:0")
-    got, ref = [], []
-    for c in range(3):
-        got.append(E[c][tidx].double().cpu().numpy())
-        ref.append(_synth(modes, [e for e, _ in exact], c, idx, shape))
-    for c in range(3):
-        got.append(B[c][tidx].double().cpu().numpy())
-        ref.append(_synth(modes, [b for _, b in exact], c, idx, shape))
-    err = rel_l2(got, ref)
-    say(f"  rel L2 over {NSAMPLE} sampled points = {err:.3e}")
+    amps = _exact(md, K, p.dt, sources)
+    nz, ny, nx = shape
+    planes = [(0, 0), (0, 1), (0, nz // 2 - 1), (0, nz - 1), (0, int(rng.integers(nz))),
+              (1, 0), (1, ny - 1), (1, int(rng.integers(ny))),
+              (2, 0), (2, nx - 1), (2, int(rng.integers(nx)))]
+    got = [np.concatenate([_gpu_plane(t, shape, a, q).ravel() for a, q in planes]) for t in E + B]
+    ref = [np.concatenate([_plane(md["m"], amps[:, c], shape, a, q).ravel() for a, q in planes])
+           for c in range(6)]
+    err = compare(([got[:3]], [got[3:]]), ([ref[:3]], [ref[3:]]),
+                  f"{len(planes)} planes, {got[0].size} points")
     assert err < 1e-5
 
 
-def test_fullsize_batched_256_patches_vs_oracle():
-    """All 256 patches of the batched workload, one plan, 2 steps, each patch
-    against the oracle (FP32 storage; oracle on the FP32-rounded inputs)."""
+def test_fullsize_batched_256_patches_500_steps_vs_oracle():
+    """All 256 patches of the batched workload, one plan (graph, autotuned, as
+    bench.py times it), 500 vacuum steps, each patch and component against one
+    oracle step of 500 dt on the FP32-rounded inputs."""
     import torch
     w = fixtures.workload(3)
-    say(f"workload 3: {len(w.patches)} patches, {w.cells} cells, 2 steps")
-    plan = pk.Plan(w.patches, precision="fp32", source_mode="vacuum", path="fused")
+    K = w.steps
+    say(f"workload 3: {len(w.patches)} patches, {w.cells} cells, {K} steps")
+    plan = pk.Plan(w.patches, precision="fp32", source_mode="vacuum", path="fused", graph=True,
+                   autotune=True)
 
     def pack(arrs):
         flat = np.zeros(plan.total_elements, np.float32)
@@ -176,25 +203,21 @@ def test_fullsize_batched_256_patches_vs_oracle():
 
     E = [pack([w.E0[i][c] for i in range(len(w.patches))]) for c in range(3)]
     B = [pack([w.B0[i][c] for i in range(len(w.patches))]) for c in range(3)]
-    plan.push(E, B, steps=2)
+    plan.push(E, B, steps=K)
     torch.cuda.synchronize()
     host = [t.cpu().numpy().astype(np.float64) for t in E + B]
     offs = list(plan.offsets)
     plan.close()
-    num = den = 0.0
-    worst = 0.0
+    gE, gB, rE, rB = [], [], [], []
     for i, p in enumerate(w.patches):
         E0 = [np.asarray(a, np.float32).astype(np.float64) for a in w.E0[i]]
         B0 = [np.asarray(a, np.float32).astype(np.float64) for a in w.B0[i]]
-        Er, Br = oracle.psatd_run(E0, B0, 2, d=p.d, dt=p.dt)
+        Er, Br = oracle.psatd_step(E0, B0, d=p.d, dt=K * p.dt)
         got = [h[offs[i]:offs[i] + p.cells].reshape(p.shape) for h in host]
-        ref = Er + Br
-        n_i = sum(float(np.sum((g - r) ** 2)) for g, r in zip(got, ref))
-        d_i = sum(float(np.sum(r * r)) for r in ref)
-        num += n_i
-        den += d_i
-        worst = max(worst, np.sqrt(n_i / d_i))
-    err = np.sqrt(num / den)
-    say(f"  rel L2 over all patches = {err:.3e}, worst patch = {worst:.3e}")
+        gE.append(got[:3])
+        gB.append(got[3:])
+        rE.append(Er)
+        rB.append(Br)
+    err = compare((gE, gB), (rE, rB), f"{len(w.patches)} patches after {K} steps")
     assert err < 1e-5
-    assert worst < 1e-5
+

@@ -1,0 +1,158 @@
+"""GPU parity on the workloads' own synthetic fields at their stated step
+counts, checked per component (and per patch) against the FP64 oracle.
+
+- 3D 512^3 (200 steps): the workload's laser and current sheet at full size.
+  Vacuum: 200 GPU steps against one oracle step of 200 dt.  With sources: J
+  held at J^(1/2) and rho linear in time (rho^n = -n dt div J, exact discrete
+  continuity), 200 GPU steps against one oracle step of 200 dt with the same J
+  and rho_new = -200 dt div J.  (The update is the exact flow of each mode over
+  a step with J constant and rho linear, so K steps equal one step of K dt;
+  the oracle's semigroup pins cover that identity.)
+- 3D 512^3 workload at 64^3 with its own time-dependent sources, 200 steps,
+  FP32 fused and FP64 plain, step by step against the oracle.
+- 3D 1024 x 1024 x 512 workload: the same-seed run at 64^3 (same spacing,
+  time step, seed and generator), 100 steps with its sources, FP32 fused and
+  FP64 plain against the oracle.
+- Batched 2D patches: the plain FP64 path on all 256 patches for the stated
+  500 steps against one oracle step of 500 dt per patch, at 1e-12.
+- No Courant condition on the generic 3D kernels: c dt = 5 dx and 20 dx.
+"""
+
+import numpy as np
+import pytest
+
+import fixtures
+import oracle
+import paper_1608_05739_amd as pk
+from gpu_support import compare, field_error, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12}
+
+
+def _dev(a, dtype=np.float32):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype).ravel()).to("cuda:0")
+
+
+def _host(t, shape):
+    return t.detach().cpu().numpy().astype(np.float64).reshape(shape)
+
+
+@pytest.fixture(scope="module")
+def w2():
+    say("generating the 512^3 workload (laser, current sheet) ...")
+    return fixtures.workload(2)
+
+
+def test_workload2_fullsize_200_vacuum_steps(w2):
+    import torch
+    p = w2.patches[0]
+    K = w2.steps
+    say(f"512^3 workload fields, vacuum, {K} steps (graph) vs one oracle step of {K} dt")
+    plan = pk.Plan([p], precision="fp32", source_mode="vacuum", path="fused", graph=True)
+    E = [_dev(a) for a in w2.E0[0]]
+    B = [_dev(a) for a in w2.B0[0]]
+    plan.push(E, B, steps=K)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    del E, B
+    E0 = [np.asarray(a, np.float32).astype(np.float64) for a in w2.E0[0]]
+    B0 = [np.asarray(a, np.float32).astype(np.float64) for a in w2.B0[0]]
+    En, Bn = oracle.psatd_step(E0, B0, d=p.d, dt=K * p.dt)
+    assert field_error(got, En + Bn) < 1e-5
+
+
+def test_workload2_fullsize_200_steps_constant_current(w2):
+    import torch
+    p = w2.patches[0]
+    K = w2.steps
+    J, _ro, rn = w2.schedule[0].sources(0, dtype=np.float64)  # rho^0 = 0, rho^1 = -dt div J
+    J32 = [np.asarray(a, np.float32) for a in J]
+    divJ32 = np.asarray(-rn / p.dt, np.float32)
+    del rn
+    say(f"512^3 workload fields, rho form, constant J, linear rho, {K} steps vs one oracle step")
+    plan = pk.Plan([p], precision="fp32", source_mode="rho", path="fused")
+    E = [_dev(a) for a in w2.E0[0]]
+    B = [_dev(a) for a in w2.B0[0]]
+    Jd = [_dev(a) for a in J32]
+    dd = _dev(divJ32)
+    ro = torch.empty_like(dd)
+    rn_d = torch.empty_like(dd)
+    for n in range(K):
+        torch.mul(dd, -n * p.dt, out=ro)
+        torch.mul(dd, -(n + 1) * p.dt, out=rn_d)
+        plan.push(E, B, Jd, ro, rn_d, steps=1)
+    torch.cuda.synchronize()
+    got = [_host(t, p.shape) for t in E + B]
+    plan.close()
+    del E, B, Jd, dd, ro, rn_d
+    E0 = [np.asarray(a, np.float32).astype(np.float64) for a in w2.E0[0]]
+    B0 = [np.asarray(a, np.float32).astype(np.float64) for a in w2.B0[0]]
+    Jo = [a.astype(np.float64) for a in J32]
+    rho_new = -K * p.dt * divJ32.astype(np.float64)
+    En, Bn = oracle.psatd_step(E0, B0, Jo, np.zeros_like(rho_new), rho_new, d=p.d, dt=K * p.dt)
+    assert field_error(got, En + Bn) < 1e-5
+
+
+@pytest.mark.parametrize("index", [2, 4])
+@pytest.mark.parametrize("precision,path", [("fp32", "fused"), ("fp64", "plain")])
+def test_3d_workload_at_64cubed_stated_steps(index, precision, path):
+    """Workload 2 (200 steps) and the same-seed 64^3 run of workload 4 (100
+    steps), with their own time-dependent sources, step by step."""
+    w = fixtures.workload(index, shape=(64, 64, 64))
+    say(f"workload {index} at 64^3, {w.steps} steps, {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps),
+                  f"workload {index} 64^3 {precision}")
+    assert err < TOL[precision]
+
+
+def test_workload3_fp64_plain_500_steps_vs_oracle():
+    import torch
+    w = fixtures.workload(3)
+    K = w.steps
+    say(f"workload 3 fp64 plain: {len(w.patches)} patches, {K} steps vs one oracle step of {K} dt")
+    plan = pk.Plan(w.patches, precision="fp64", source_mode="vacuum", path="plain", graph=True)
+
+    def pack(arrs):
+        flat = np.zeros(plan.total_elements, np.float64)
+        for off, a in zip(plan.offsets, arrs):
+            flat[off:off + a.size] = np.asarray(a, np.float64).ravel()
+        return torch.from_numpy(flat).to("cuda:0")
+
+    E = [pack([w.E0[i][c] for i in range(len(w.patches))]) for c in range(3)]
+    B = [pack([w.B0[i][c] for i in range(len(w.patches))]) for c in range(3)]
+    plan.push(E, B, steps=K)
+    torch.cuda.synchronize()
+    host = [t.cpu().numpy() for t in E + B]
+    offs = list(plan.offsets)
+    plan.close()
+    gE, gB, rE, rB = [], [], [], []
+    for i, p in enumerate(w.patches):
+        Er, Br = oracle.psatd_step(list(w.E0[i]), list(w.B0[i]), d=p.d, dt=K * p.dt)
+        got = [h[offs[i]:offs[i] + p.cells].reshape(p.shape) for h in host]
+        gE.append(got[:3])
+        gB.append(got[3:])
+        rE.append(Er)
+        rB.append(Br)
+    assert compare((gE, gB), (rE, rB), f"{len(w.patches)} patches fp64") < 1e-12
+
+
+@pytest.mark.parametrize("cdt", [5.0, 20.0])
+@pytest.mark.parametrize("precision,path", [("fp32", "fused"), ("fp64", "plain")])
+def test_3d_generic_large_time_step(cdt, precision, path):
+    """No Courant condition (Table 1, PSATD row) on the generic 3D kernels:
+    c dt = 5 dx and 20 dx, with sources, 3 steps against the oracle."""
+    w0 = fixtures.workload(2, shape=(48, 32, 64), steps=3)
+    p0 = w0.patches[0]
+    dt = cdt * p0.dx
+    p = fixtures.workloads.Patch(3, p0.nx, p0.ny, p0.nz, p0.dx, p0.dy, p0.dz, dt)
+    s = w0.schedule[0]
+    sched = [fixtures.SourceSchedule(s.P, s.D, s.phases, dt)]
+    say(f"3D {p.shape} c dt = {cdt} dx, {precision} {path}, 3 steps")
+    err = compare(run_gpu(w0, precision, path, 3, patches=[p], schedule=sched),
+                  run_oracle(w0, precision, 3, patches=[p], schedule=sched),
+                  f"c dt = {cdt} dx")
+    assert err < TOL[precision]
