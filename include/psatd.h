@@ -65,7 +65,12 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
 
 /* psatd_config.flags */
 #define PSATD_FLAG_AUTOTUNE 0x1u /* time each pass at several grid sizes at plan time (on scratch fields), keep the fastest */
-#define PSATD_FLAG_GRAPH 0x2u    /* replay a captured hipGraph of one step inside psatd_push   */
+/* Capture one step into a hipGraph at plan time (or in psatd_set_workspace when
+ * the plan has no workspace yet); psatd_push then writes the field pointers
+ * into a plan-owned device table (one small kernel) and replays the graph
+ * nsteps times.  Pushes on a stream that the caller is capturing enqueue the
+ * kernels themselves instead, so that the caller's graph records them. */
+#define PSATD_FLAG_GRAPH 0x2u
 #define PSATD_FLAG_NO_WORKSPACE 0x4u /* allocate no workspace: call psatd_set_workspace first */
 #define PSATD_FLAG_GENERIC_KERNELS 0x8u /* never pick shape-specialized kernels (cross-checks) */
 /* order p > 0: take k_p from the centered (collocated) order-p stencil,
@@ -135,15 +140,18 @@ psatd_status psatd_workspace_size(psatd_plan_t plan, size_t* bytes);
 
 /* Hand the plan a caller-owned device workspace of at least
  * psatd_workspace_size() bytes, 256-byte aligned.  Frees any plan-owned
- * workspace.  The caller keeps it alive until psatd_destroy. */
+ * workspace.  The caller keeps it alive until psatd_destroy.  With
+ * PSATD_FLAG_GRAPH this (re)captures the step graph, which allocates. */
 psatd_status psatd_set_workspace(psatd_plan_t plan, void* device_ptr, size_t bytes);
 
 /* Advance the fields by nsteps steps, asynchronously on `hip_stream` (a
  * hipStream_t; NULL = the default stream).  J is J^{n+1/2}, rho_old = rho^n,
  * rho_new = rho^{n+1}; with sources nsteps must be 1.  No allocation, host
- * synchronization or host copy happens here once the workspace exists, so the
- * call can be captured into a hipGraph.  Not thread-safe for concurrent pushes
- * on one plan. */
+ * synchronization or host copy happens here once the workspace exists (with
+ * PSATD_FLAG_GRAPH as well: the graph was built beforehand), so the call can
+ * be captured into a caller's hipGraph.  Not thread-safe for concurrent
+ * pushes on one plan: with PSATD_FLAG_GRAPH, pushes of different fields on
+ * different streams would race on the plan's field table. */
 psatd_status psatd_push(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
                         void* hip_stream);
 

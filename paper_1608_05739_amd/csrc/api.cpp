@@ -162,8 +162,7 @@ struct psatd_plan_s {
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
-  FieldPtrs graph_fields{};
-  hipStream_t graph_stream = nullptr;
+  FieldPtrs* d_fieldtab = nullptr;  // field pointers the graph's kernels read (FieldPtrs::table)
   std::string info;
 };
 
@@ -176,6 +175,7 @@ void free_plan_memory(psatd_plan_s* p) {
   if (p->d_patches) (void)hipFree(p->d_patches);
   if (p->d_tables) (void)hipFree(p->d_tables);
   if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_fieldtab) (void)hipFree(p->d_fieldtab);
   for (void* x : p->extra_items) (void)hipFree(x);
   p->extra_items.clear();
   if (p->ws && p->ws_owned) (void)hipFree(p->ws);
@@ -185,6 +185,7 @@ void free_plan_memory(psatd_plan_s* p) {
   p->d_patches = nullptr;
   p->d_tables = nullptr;
   p->d_items = nullptr;
+  p->d_fieldtab = nullptr;
   p->ws = nullptr;
 }
 
@@ -659,8 +660,54 @@ psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStre
   return PSATD_OK;
 }
 
-bool same_fields(const FieldPtrs& a, const FieldPtrs& b) {
-  return std::memcmp(&a, &b, sizeof(FieldPtrs)) == 0;
+// PSATD_FLAG_GRAPH: capture one step into a graph whose kernels read the
+// field pointers from the plan's device table, and instantiate it.  Runs at
+// plan time and in psatd_set_workspace (the step needs the workspace), so
+// that a push only writes the table and launches the graph: no allocation,
+// no capture, for any fields.
+psatd_status build_graph(psatd_plan_s* plan) {
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  plan->graph_exec = nullptr;
+  plan->graph = nullptr;
+  if (!plan->ws) return PSATD_OK;  // built when the workspace arrives
+  hipError_t e = hipSuccess;
+  if (!plan->d_fieldtab) {
+    e = hipMalloc(&plan->d_fieldtab, sizeof(FieldPtrs));
+    if (e != hipSuccess) {
+      plan->d_fieldtab = nullptr;
+      return hip_fail(e, "hipMalloc(field table)");
+    }
+    e = hipMemset(plan->d_fieldtab, 0, sizeof(FieldPtrs));
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(field table)");
+  }
+  if (!plan->capture_stream) {
+    e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      plan->capture_stream = nullptr;
+      return hip_fail(e, "capture stream");
+    }
+  }
+  FieldPtrs fp{};
+  fp.table = plan->d_fieldtab;
+  e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  psatd_status cs = enqueue_step(plan, fp, plan->capture_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(plan->capture_stream, &graph);
+  if (cs != PSATD_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return cs;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    plan->graph_exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  plan->graph = graph;
+  return PSATD_OK;
 }
 
 // Launch-shape autotuning (PSATD_FLAG_AUTOTUNE).  Every kernel loops over its
@@ -1002,6 +1049,10 @@ psatd_status build_plan(psatd_plan_s* plan) {
     psatd_status st = autotune_passes(plan);
     if (st != PSATD_OK) return st;
   }
+  if (cfg.flags & PSATD_FLAG_GRAPH) {
+    psatd_status st = build_graph(plan);
+    if (st != PSATD_OK) return st;
+  }
 
   char buf[512];
   plan->info.clear();
@@ -1094,12 +1145,7 @@ psatd_status psatd_set_workspace(psatd_plan_t plan, void* ptr, size_t bytes) {
   if (plan->ws && plan->ws_owned) (void)hipFree(plan->ws);
   plan->ws = ptr;
   plan->ws_owned = false;
-  if (plan->graph_exec) {
-    (void)hipGraphExecDestroy(plan->graph_exec);
-    (void)hipGraphDestroy(plan->graph);
-    plan->graph_exec = nullptr;
-    plan->graph = nullptr;
-  }
+  if (plan->cfg.flags & PSATD_FLAG_GRAPH) return build_graph(plan);
   return PSATD_OK;
 }
 
@@ -1148,40 +1194,21 @@ static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int
   }
 
   if (plan->cfg.flags & PSATD_FLAG_GRAPH) {
-    if (!plan->graph_exec || !same_fields(plan->graph_fields, fp)) {
-      if (plan->graph_exec) {
-        (void)hipGraphExecDestroy(plan->graph_exec);
-        (void)hipGraphDestroy(plan->graph);
-        plan->graph_exec = nullptr;
-        plan->graph = nullptr;
+    // A stream the caller is capturing records the kernels themselves;
+    // otherwise write the field table and replay the plan's graph.
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cst);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cst == hipStreamCaptureStatusNone) {
+      if (!plan->graph_exec) return fail(PSATD_ERR_STATE, "graph plan without its graph");
+      e = launch_store_fields(fp, plan->d_fieldtab, s);
+      if (e != hipSuccess) return hip_fail(e, "field table");
+      for (int n = 0; n < nsteps; ++n) {
+        e = hipGraphLaunch(plan->graph_exec, s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
       }
-      if (!plan->capture_stream) {
-        hipError_t e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return hip_fail(e, "capture stream");
-      }
-      hipError_t e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      psatd_status cs = enqueue_step(plan, fp, plan->capture_stream);
-      hipGraph_t graph = nullptr;
-      e = hipStreamEndCapture(plan->capture_stream, &graph);
-      if (cs != PSATD_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return cs;
-      }
-      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-      e = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return hip_fail(e, "hipGraphInstantiate");
-      }
-      plan->graph = graph;
-      plan->graph_fields = fp;
+      return PSATD_OK;
     }
-    for (int n = 0; n < nsteps; ++n) {
-      hipError_t e = hipGraphLaunch(plan->graph_exec, s);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    }
-    return PSATD_OK;
   }
 
   for (int n = 0; n < nsteps; ++n) {

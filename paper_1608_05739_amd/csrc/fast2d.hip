@@ -200,7 +200,7 @@ __device__ __forceinline__ double2 ld_f2(const float2* p) {
 
 __device__ __forceinline__ const float2* x_row(const PatchDev* P, const FieldPtrs& fields,
                                                const WorkItem& wi, int w) {
-  return reinterpret_cast<const float2*>(static_cast<const float*>(fields.f[wi.comp]) +
+  return reinterpret_cast<const float2*>(static_cast<const float*>(field_ptr(fields, wi.comp)) +
                                          P->off_real + (long long)(wi.first + kN1 * w) * (2 * kMX));
 }
 
@@ -409,7 +409,7 @@ x_inv_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ 
     wave_lds_sync();
     double2 c[4][8];
     wave_fft2048<1>(region, a, c, twB, twC);
-    float2* row = reinterpret_cast<float2*>(static_cast<float*>(fields.f[wi.comp]) + P->off_real +
+    float2* row = reinterpret_cast<float2*>(static_cast<float*>(field_ptr(fields, wi.comp)) + P->off_real +
                                             (long long)(z1 + kN1 * w) * (2 * kMX));
 #pragma unroll
     for (int b = 0; b < 4; ++b)

@@ -87,10 +87,19 @@ __device__ __forceinline__ int xcd_local_order(int b, int n) {
   return base + (r & 7) * 32 + (r >> 3);
 }
 
-// Caller field pointers (real arrays), indexed by Comp.
+// Caller field pointers (real arrays), indexed by Comp.  When `table` is
+// set, the kernels read the pointers from that device copy instead of from
+// f: a step captured once into a graph then serves any fields, the push
+// writing the current pointers into the table first (see field_ptr).
 struct FieldPtrs {
   void* f[kMaxComp];
+  const FieldPtrs* table;
 };
+
+// Pointer of component c as a kernel sees it.
+__device__ __forceinline__ void* field_ptr(const FieldPtrs& fields, int c) {
+  return fields.table ? fields.table->f[c] : fields.f[c];
+}
 
 struct Physics {
   double c;

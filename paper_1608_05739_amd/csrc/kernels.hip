@@ -236,7 +236,7 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
       } else {
         // x rows (real pairs) or z lines: the tile is contiguous
         const V* src = KIND == kXFwd
-                           ? reinterpret_cast<const V*>(static_cast<const S*>(fields.f[wi.comp]) +
+                           ? reinterpret_cast<const V*>(static_cast<const S*>(field_ptr(fields, wi.comp)) +
                                                         P->off_real)
                            : spec;
         src += (long long)l0 * L;
@@ -267,7 +267,7 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
         spec_out[tile_offset(tm, l0 + r, n)] = from_d2<V>(lds[lpad(r * LS + n)]);
       }
     } else if constexpr (KIND == kXInv) {
-      V* dst = reinterpret_cast<V*>(static_cast<S*>(fields.f[wi.comp]) + P->off_real);
+      V* dst = reinterpret_cast<V*>(static_cast<S*>(field_ptr(fields, wi.comp)) + P->off_real);
       for (Walk2 w(L); w.hi < nl; w.next())
         dst[(long long)(l0 + w.hi) * L + w.lo] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);
     } else if constexpr (KIND == kYInv) {
@@ -536,6 +536,22 @@ __global__ void ktable_kernel(double* k, int n, double d, int count, int packed_
   }
   if (nyquist || (packed_x && j == 0)) kv = 0.0;
   k[j] = kv;
+}
+
+// ------------------------------------------------------------------ field table
+// Writes the caller's field pointers into the plan's device table (one
+// thread; the push enqueues it ahead of a graph whose kernels read the table).
+__global__ void store_fields_kernel(FieldPtrs f, FieldPtrs* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) dst->f[c] = f.f[c];
+    dst->table = nullptr;
+  }
+}
+
+hipError_t launch_store_fields(const FieldPtrs& f, FieldPtrs* dst, hipStream_t stream) {
+  hipLaunchKernelGGL(store_fields_kernel, dim3(1), dim3(64), 0, stream, f, dst);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ launchers

@@ -58,6 +58,9 @@ hipError_t launch_ktable(double* k, int n, double d, int count, int packed_x,
                          const double* fornberg, int nfornberg, int centered,
                          hipStream_t stream);
 
+// Copy the caller's field pointers into a device table (FieldPtrs::table).
+hipError_t launch_store_fields(const FieldPtrs& f, FieldPtrs* dst, hipStream_t stream);
+
 // Raise the dynamic-LDS limit of every kernel instantiation (once per process).
 hipError_t configure_kernel_attributes();
 

@@ -109,54 +109,73 @@ def run_oracle(w, precision, steps, form="rho", order=0, patches=None, E0=None, 
 
 COMPONENTS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
+# Coupled sets of components.  In 2D (k_y = 0) the update never mixes the
+# s-polarized set (Ey, Bx, Bz) with the p-polarized set (Ex, Ez, By); in 3D
+# every component couples with every other.
+GROUPS_2D = ((1, 3, 5), (0, 2, 4))
+GROUPS_3D = ((0, 1, 2, 3, 4, 5),)
 
-def component_errors(got, ref):
+# Tolerances.  GROUP: each component's error against the norm (and largest
+# value) of its coupled set -- the FP32 target of 1e-5 and the FP64 target
+# of 1e-12.  OWN: each component's error against its own norm.  With FP32
+# storage every step rounds each component to 24 bits, and the update feeds
+# each component from the rest of its set with coefficients of order one, so
+# a component much smaller than its set carries a rounding floor of about
+# 6e-8 x (set norm / own norm) x sqrt(steps) relative to itself (measured
+# 1e-5 .. 5e-4 on the smallest components of the tests; the CPU model in
+# test_parity_measure.py reproduces it).  1e-3 still fails any wrong term,
+# which misses by O(1) of the component.  In FP64 the floor is far below
+# 1e-12, so both bounds are 1e-12.
+GROUP_TOL = {"fp32": 1e-5, "fp64": 1e-12}
+OWN_TOL = {"fp32": 1e-3, "fp64": 1e-12}
+
+
+def component_errors(got, ref, groups=None):
     """Per-component errors of one patch: got, ref = six arrays (E then B).
 
-    For a component whose reference is not identically zero: the relative L2
-    error against that component's own norm, and the largest pointwise error
-    over that component's own largest value.  For an identically zero
-    reference: the output's norm over the norm of all six reference
-    components (it must stay at rounding).  Returns {name: (rel_l2, max_rel)}.
+    Returns {name: (own, group, group_max)}: the relative L2 error against
+    the component's own norm (an identically zero reference is measured
+    against its set's norm instead), against the norm of its coupled set, and
+    the largest pointwise error over the set's largest value.  ``groups``
+    defaults to the 2D sets for 2D arrays and one set for anything else.
     """
-    total = np.sqrt(sum(float(np.sum(np.asarray(r, np.float64) ** 2)) for r in ref))
+    got = [np.asarray(g, np.float64) for g in got]
+    ref = [np.asarray(r, np.float64) for r in ref]
+    if groups is None:
+        groups = GROUPS_2D if ref[0].ndim == 2 else GROUPS_3D
     out = {}
-    for name, g, r in zip(COMPONENTS, got, ref):
-        g = np.asarray(g, np.float64)
-        r = np.asarray(r, np.float64)
-        nr = float(np.sqrt(np.sum(r * r)))
-        if nr == 0.0:
-            e = float(np.sqrt(np.sum(g * g))) / max(total, 1e-300)
-            out[name] = (e, e)
-        else:
-            d = g - r
-            out[name] = (float(np.sqrt(np.sum(d * d))) / nr,
-                         float(np.max(np.abs(d))) / float(np.max(np.abs(r))))
+    for grp in groups:
+        gnorm = np.sqrt(sum(float(np.sum(ref[c] ** 2)) for c in grp))
+        gmax = max(float(np.max(np.abs(ref[c]))) for c in grp)
+        for c in grp:
+            d = got[c] - ref[c]
+            err = float(np.sqrt(np.sum(d * d)))
+            own = float(np.sqrt(np.sum(ref[c] ** 2)))
+            e_grp = err / max(gnorm, 1e-300)
+            m_grp = float(np.max(np.abs(d))) / max(gmax, 1e-300)
+            out[COMPONENTS[c]] = (err / own if own > 0.0 else e_grp, e_grp, m_grp)
     return out
 
 
-def compare(gpu, ref, label=None):
+def compare(gpu, ref, label=None, precision="fp32", groups=None):
     """Worst error over every patch and every component of (E, B).
 
-    Each component of each patch is measured against its own scale
-    (``component_errors``): the relative L2 error and the largest pointwise
-    error relative to the component's largest value; a component whose
-    reference is identically zero is measured against the patch's field norm.
-    Returns the largest of all these, so that a wrong low-amplitude component
-    cannot hide behind the others.  Prints the per-component worst values.
+    Each component of each patch is measured by ``component_errors``.  The
+    value returned is the largest of the coupled-set errors and of the
+    own-norm errors scaled by GROUP_TOL / OWN_TOL, so that the tests'
+    ``err < GROUP_TOL[precision]`` asserts both bounds.  Prints the worst
+    own-norm and coupled-set errors of each component.
     """
     (gE, gB), (rE, rB) = gpu, ref
-    worst = {c: (0.0, 0.0, -1) for c in COMPONENTS}
-    for p, (ge, gb, re_, rb) in enumerate(zip(gE, gB, rE, rB)):
-        for name, (e2, em) in component_errors(list(ge) + list(gb), list(re_) + list(rb)).items():
-            w2, wm, _ = worst[name]
-            if max(e2, em) > max(w2, wm):
-                worst[name] = (e2, em, p)
-            else:
-                worst[name] = (max(w2, e2), max(wm, em), worst[name][2])
-    text = ", ".join(f"{c} {v[0]:.2e}/{v[1]:.2e}" for c, v in worst.items())
-    say(f"  {label + ': ' if label else ''}per component rel L2 / max rel: {text}")
-    return max(max(v[0], v[1]) for v in worst.values())
+    scale = GROUP_TOL[precision] / OWN_TOL[precision]
+    worst = {c: [0.0, 0.0, 0.0] for c in COMPONENTS}
+    for ge, gb, re_, rb in zip(gE, gB, rE, rB):
+        errs = component_errors(list(ge) + list(gb), list(re_) + list(rb), groups)
+        for name, v in errs.items():
+            worst[name] = [max(a, b) for a, b in zip(worst[name], v)]
+    text = ", ".join(f"{c} {v[0]:.1e}/{max(v[1], v[2]):.1e}" for c, v in worst.items())
+    say(f"  {label + ': ' if label else ''}per component (own / coupled set): {text}")
+    return max(max(v[1], v[2], v[0] * scale) for v in worst.values())
 
 
 def compare_global(gpu, ref):
@@ -168,6 +187,7 @@ def compare_global(gpu, ref):
     return rel_l2(a, b)
 
 
-def field_error(got, ref, label=None):
+def field_error(got, ref, label=None, precision="fp32", groups=None):
     """``compare`` for one patch given as six arrays (Ex, Ey, Ez, Bx, By, Bz)."""
-    return compare(([list(got[:3])], [list(got[3:])]), ([list(ref[:3])], [list(ref[3:])]), label)
+    return compare(([list(got[:3])], [list(got[3:])]), ([list(ref[:3])], [list(ref[3:])]), label,
+                   precision, groups)

@@ -30,8 +30,8 @@ def _w(index, shape, steps):
 def test_workload0_vacuum_128(precision, path):
     w = fixtures.workload(0)
     say(f"workload0 {precision} {path} 128x128 x {w.steps} steps")
-    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
-    say(f"  rel L2 = {err:.3e}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
     assert err < TOL[precision]
 
 
@@ -45,8 +45,8 @@ SHAPES_2D = [(48, 64), (6, 8), (12, 18), (18, 12), (96, 64), (64, 96), (2, 4), (
 def test_2d_sources_rho(shape, precision, path):
     w = _w(1, shape, 6)
     say(f"2d rho {shape} {precision} {path}")
-    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
-    say(f"  rel L2 = {err:.3e}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
     assert err < TOL[precision]
 
 
@@ -56,7 +56,8 @@ def test_2d_sources_jform(shape, precision, path):
     w = _w(1, shape, 5)
     say(f"2d J-form {shape} {precision} {path}")
     err = compare(run_gpu(w, precision, path, w.steps, form="J"),
-                  run_oracle(w, precision, w.steps, form="J"))
+                  run_oracle(w, precision, w.steps, form="J"),
+                  precision=precision)
     assert err < TOL[precision]
 
 
@@ -70,8 +71,8 @@ SHAPES_3D = [(8, 6, 12), (12, 8, 18), (16, 16, 16), (6, 12, 8)]
 def test_3d_sources_rho(shape, precision, path):
     w = _w(2, shape, 4)
     say(f"3d rho {shape} {precision} {path}")
-    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
-    say(f"  rel L2 = {err:.3e}")
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
     assert err < TOL[precision]
 
 
@@ -80,7 +81,8 @@ def test_3d_vacuum_plane_waves(precision, path):
     w = fixtures.workload(4, shape=(16, 24, 32), steps=6)
     w.sources = False
     say(f"3d vacuum packets {precision} {path}")
-    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
+    err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
     assert err < TOL[precision]
 
 
@@ -89,7 +91,7 @@ def test_order_p(order):
     w = _w(1, (32, 48), 4)
     say(f"order {order}")
     err = compare(run_gpu(w, "fp64", "plain", w.steps, order=order),
-                  run_oracle(w, "fp64", w.steps, order=order))
+                  run_oracle(w, "fp64", w.steps, order=order), precision="fp64")
     assert err < TOL["fp64"]
 
 
@@ -106,8 +108,8 @@ def test_radix4_line_passes(index, shape, precision, path):
     w = _w(index, shape, 3)
     say(f"radix-4 lines {shape} {precision} {path}")
     err = compare(run_gpu(w, precision, path, w.steps, radix4_lines=True),
-                  run_oracle(w, precision, w.steps))
-    say(f"  rel L2 = {err:.3e}")
+                  run_oracle(w, precision, w.steps),
+                  precision=precision)
     assert err < TOL[precision]
 
 
@@ -115,7 +117,6 @@ def test_radix4_line_passes_batched():
     w = fixtures.workload(3, npatches=24, steps=3)
     err = compare(run_gpu(w, "fp32", "fused", w.steps, radix4_lines=True),
                   run_oracle(w, "fp32", w.steps))
-    say(f"radix-4 lines, 24 batched patches: rel L2 = {err:.3e}")
     assert err < TOL["fp32"]
 
 
@@ -134,7 +135,6 @@ def test_fused_modes_per_thread_fallbacks(index, shape, mpt):
     assert f"mpt={mpt} " in info, info
     say(f"fused fp32 {shape}: mpt={mpt}")
     err = compare(run_gpu(w, "fp32", "fused", w.steps), run_oracle(w, "fp32", w.steps))
-    say(f"  rel L2 = {err:.3e}")
     assert err < TOL["fp32"]
 
 
@@ -143,8 +143,8 @@ def test_batched_patches_workload3_subset():
     w = fixtures.workload(3, npatches=24, steps=3)
     say(f"batched 24 patches, {w.cells} cells")
     for precision, path in (("fp32", "fused"), ("fp64", "plain")):
-        err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps))
-        say(f"  {precision} {path}: rel L2 = {err:.3e}")
+        err = compare(run_gpu(w, precision, path, w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
         assert err < TOL[precision]
 
 

@@ -23,7 +23,20 @@ def test_small_component_error_is_flagged():
     pooled = np.sqrt(sum(np.sum((g - r) ** 2) for g, r in zip(got, ref))
                      / sum(np.sum(r * r) for r in ref))
     assert pooled < 1e-5
-    assert compare(([got[:3]], [got[3:]]), ([ref[:3]], [ref[3:]])) > 5e-3
+    # fails the FP32 bounds (own norm 1e-3) and the FP64 ones
+    assert compare(([got[:3]], [got[3:]]), ([ref[:3]], [ref[3:]])) > 1e-5
+    assert compare(([got[:3]], [got[3:]]), ([ref[:3]], [ref[3:]]), precision="fp64") > 1e-12
+
+
+def test_s_set_error_is_flagged_against_its_own_set():
+    # a 1e-4 error on the whole s set (Ey, Bx, Bz), whose norm is 1e-2 of
+    # the p set's: pooled over all components it is 1e-6, against its set 1e-4
+    rng = np.random.default_rng(5)
+    ref = [rng.normal(size=(32, 40)) * s for s in (1.0, 1e-2, 1.0, 1e-2, 1.0, 1e-2)]
+    got = [r.copy() for r in ref]
+    for c in (1, 3, 5):
+        got[c] *= 1 + 1e-4
+    assert compare(([got[:3]], [got[3:]]), ([ref[:3]], [ref[3:]])) > 5e-5
 
 
 def test_single_wrong_point_is_flagged():
@@ -32,7 +45,7 @@ def test_single_wrong_point_is_flagged():
     got = [r.copy() for r in ref]
     got[1][7, 9] += 1e-3 * np.max(np.abs(ref[1]))
     e = component_errors(got, ref)["Ey"]
-    assert e[1] > 9e-4 and e[0] < 1e-4
+    assert e[2] > 4e-4 and e[0] < 1e-4
 
 
 def test_nonzero_output_over_zero_reference_is_flagged():
@@ -40,7 +53,7 @@ def test_nonzero_output_over_zero_reference_is_flagged():
     ref = _ref(rng)
     ref[1] = np.zeros_like(ref[1])
     got = [r.copy() for r in ref]
-    assert component_errors(got, ref)["Ey"] == (0.0, 0.0)
+    assert component_errors(got, ref)["Ey"] == (0.0, 0.0, 0.0)
     got[1][0, 0] = 1e-3
     assert component_errors(got, ref)["Ey"][0] > 1e-6
 
@@ -52,4 +65,36 @@ def test_worst_patch_decides():
     gots[2][4] *= 1 + 1e-4
     err = compare(([g[:3] for g in gots], [g[3:] for g in gots]),
                   ([r[:3] for r in refs], [r[3:] for r in refs]))
-    assert 5e-5 < err < 2e-4
+    assert 1e-5 < err < 2e-4
+
+
+def test_fp32_storage_floor_model():
+    """Why FP32 tolerances are set per coupled set: the oracle itself, with
+    only its fields rounded to FP32 after every step (any FP32-storage
+    implementation does at least that), puts a small s-polarized component
+    (Bz on a 2 x 4 grid with sources) 4e-4 of its own norm away from the FP64
+    run, while every component stays within 1e-7 of its coupled set's norm.
+    The GPU tests therefore bound FP32 errors by 1e-5 of the coupled set and
+    1e-3 of the component's own norm (tests/gpu_support.py)."""
+    import fixtures
+    import oracle
+    from gpu_support import GROUP_TOL, OWN_TOL
+
+    w = fixtures.workload(1, shape=(2, 4), steps=6)
+    p = w.patches[0]
+    E0 = [np.asarray(a, np.float32).astype(np.float64) for a in w.E0[0]]
+    B0 = [np.asarray(a, np.float32).astype(np.float64) for a in w.B0[0]]
+    ref = oracle.psatd_run(E0, B0, 6, d=p.d, dt=p.dt, schedule=w.schedule[0],
+                           source_dtype=np.float32)
+
+    def to_fp32(n, E, B):
+        for a in E + B:
+            a[...] = a.astype(np.float32)
+
+    got = oracle.psatd_run(E0, B0, 6, d=p.d, dt=p.dt, schedule=w.schedule[0],
+                           source_dtype=np.float32, callback=to_fp32)
+    e = component_errors(got[0] + got[1], ref[0] + ref[1])
+    assert e["Bz"][0] > 1e-4                       # own norm: far above 1e-5
+    assert all(v[1] < 1e-7 for v in e.values())    # coupled set: at rounding
+    assert max(v[0] for v in e.values()) < OWN_TOL["fp32"]
+    assert max(v[1] for v in e.values()) < GROUP_TOL["fp32"]
