@@ -1,17 +1,20 @@
 """Benchmark of the PSATD field step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
 
 A step is one full pass of the hot path (x r2c FFT of every input, fused z
-pass with the per-mode update, x c2r FFT of E and B) over the workload's
-synthetic fields, inputs resident in HBM.  Workload 1 (default): 2D 4096 x
-4096, J and rho sources (rho form), FP32 storage.  Prints ONE JSON line on
-stdout; progress goes to stderr.
+pass with the per-mode update, x c2r FFT of E and B; 3D adds the y passes)
+over the workload's synthetic fields, inputs resident in HBM.  Workload 3
+(default): 256 independent periodic 2D patches with sides from 64 to 512,
+each with its own time step, vacuum, FP32 storage, one launch per pass over
+all patches, hipGraph replay, autotuned launch shapes.  Prints ONE JSON line
+on stdout; progress goes to stderr.
 
 The line also reports, on the same workload: the plain FP64 path, the
 per-pass durations (HIP events on the launch stream), the roofline of the
-dominant kernel, a one-step parity check against the FP64 oracle, and the
-oracle's own throughput on the host cores (cpu_baseline).
+dominant kernel, and -- in the oracle leg -- the oracle's own throughput on
+the host cores (cpu_baseline) and the error of both GPU paths against the
+FP64 oracle after the run's step count, per field component.
 """
 
 from __future__ import annotations
@@ -38,14 +41,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Device-code sources of the kernels the stored traffic describes (the 4096 x
-# 4096 passes); a change to any of them makes the stored counters stale.
-KERNEL_SOURCES = ("fast2d.hip", "fast2d.hpp", "fft.hpp", "groups.hpp", "update.hpp", "internal.hpp")
+# Device-code sources of the kernels; a change to any of them makes the stored
+# traffic counters stale.
+def kernel_sources():
+    return sorted(n for n in os.listdir(CSRC) if n.endswith((".hip", ".hpp")))
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in kernel_sources():
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -66,8 +70,22 @@ def measured_traffic(workload, kernel):
     return ent.get("bytes_per_launch")
 
 
-PASS_OF_KERNEL = (("x_fwd_kernel", "x_r2c_fwd"), ("z_fused_kernel", "z_fused"),
-                  ("x_inv_kernel", "x_c2r_inv"))
+# rocprofv3 kernel names -> pass names (the 4096 x 4096 kernels and the
+# generic ones: line_pass_kernel<S, KIND, PPT>, KIND 0 x fwd, 1 x inv, 2 y fwd,
+# 3 y inv; the wave-resident 2D kernels carry the pass in their name)
+def pass_of_kernel(name):
+    import re
+    for key, pname in (("x_fwd_kernel", "x_r2c_fwd"), ("z_fused_kernel", "z_fused"),
+                       ("x_inv_kernel", "x_c2r_inv"), ("fused_z_kernel", "z_fused"),
+                       ("wave_z_fused", "z_fused"), ("wave_x_fwd", "x_r2c_fwd"),
+                       ("wave_x_inv", "x_c2r_inv")):
+        if key in name:
+            return pname
+    m = re.search(r"line_pass_kernel<[^,]+, ?(\d)", name)
+    if m:
+        return {"0": "x_r2c_fwd", "1": "x_c2r_inv", "2": "y_c2c_fwd", "3": "y_c2c_inv",
+                "4": "z_c2c_fwd", "5": "z_c2c_inv"}[m.group(1)]
+    return None
 
 
 def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
@@ -99,9 +117,10 @@ def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
     except (OSError, ValueError):
         data = {}
     h = kernel_source_hash()
-    for key, pname in PASS_OF_KERNEL:
-        fv = [v for n, v in fetch if key in n]
-        wv = [v for n, v in write if key in n]
+    passes = sorted({pass_of_kernel(n) for n, _ in fetch} - {None})
+    for pname in passes:
+        fv = [v for n, v in fetch if pass_of_kernel(n) == pname]
+        wv = [v for n, v in write if pass_of_kernel(n) == pname]
         if not fv or not wv:
             continue
         f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
@@ -175,53 +194,130 @@ def time_steps(plan, E, B, J, ro, rn, steps, warmup, vacuum_batch):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(w, budget_s, rounded_dtype):
-    """The FP64 oracle on the host cores, on the first steps of the same workload."""
+# ------------------------------------------------------------------ oracle leg
+# Everything below that calls the oracle is the cpu_baseline leg: the oracle
+# timed on the host cores, and the GPU results of the timed configuration
+# checked against it.
+def component_errors(got, ref, ndim):
+    """Per component (E then B): relative L2 error against the component's own
+    norm and against its coupled set's norm (2D: the s set Ey, Bx, Bz and the
+    p set Ex, Ez, By never mix; 3D: all six)."""
+    groups = ((1, 3, 5), (0, 2, 4)) if ndim == 2 else ((0, 1, 2, 3, 4, 5),)
+    names = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+    out = {}
+    for g in groups:
+        gn = np.sqrt(sum(float(np.sum(ref[c] ** 2)) for c in g))
+        for c in g:
+            e = float(np.sqrt(np.sum((got[c] - ref[c]) ** 2)))
+            own = float(np.sqrt(np.sum(ref[c] ** 2)))
+            out[names[c]] = (e / own if own > 0 else e / max(gn, 1e-300), e / max(gn, 1e-300))
+    return out
+
+
+def summarize(per_patch):
+    """Worst own-norm and coupled-set errors per component over the patches,
+    and the relative L2 pooled over everything."""
+    worst = {}
+    num = den = 0.0
+    for errs, n2, d2 in per_patch:
+        num += n2
+        den += d2
+        for k, (a, b) in errs.items():
+            wa, wb = worst.get(k, (0.0, 0.0))
+            worst[k] = (max(wa, a), max(wb, b))
+    return {"per_component_own": {k: v[0] for k, v in worst.items()},
+            "per_component_coupled_set": {k: v[1] for k, v in worst.items()},
+            "max_coupled_set": max(v[1] for v in worst.values()),
+            "max_own": max(v[0] for v in worst.values()),
+            "pooled": float(np.sqrt(num / max(den, 1e-300)))}
+
+
+def oracle_leg(w, budget_s, gpu_results, steps):
+    """cpu_baseline: the FP64 oracle unchanged, on the host cores, on a
+    bounded sample of the workload (its first patches / first steps within
+    ``budget_s``).  Then parity: each GPU result in ``gpu_results``
+    ({label: (precision, E, B) per patch as float64 host arrays}) against the
+    oracle.  Vacuum: K steps against one oracle step of K dt per patch (the
+    exact per-mode flow; the oracle's semigroup pins cover the identity).
+    With sources: one step with the step-0 sources."""
     import oracle
 
     workers = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cells = 0
-    steps_done = 0
+    nsteps = 0
     t0 = time.perf_counter()
-    first = None
     for pi, p in enumerate(w.patches):
-        E = [np.asarray(a, rounded_dtype).astype(np.float64) for a in w.E0[pi]]
-        B = [np.asarray(a, rounded_dtype).astype(np.float64) for a in w.B0[pi]]
+        E = [np.asarray(a, np.float32).astype(np.float64) for a in w.E0[pi]]
+        B = [np.asarray(a, np.float32).astype(np.float64) for a in w.B0[pi]]
         n = 0
         while True:
+            J = ro = rn = None
             if w.sources:
-                J, ro, rn = w.schedule[pi].sources(0, dtype=rounded_dtype)
+                J, ro, rn = w.schedule[pi].sources(n, dtype=np.float32)
                 J = [np.asarray(a, np.float64) for a in J]
                 ro, rn = np.asarray(ro, np.float64), np.asarray(rn, np.float64)
-            else:
-                J = ro = rn = None
             E, B = oracle.psatd_step(E, B, J, ro, rn, d=p.d, dt=p.dt, workers=workers)
             n += 1
             cells += p.cells
-            if pi == 0 and n == 1:
-                first = (E, B)
-            if time.perf_counter() - t0 > budget_s or n >= 1000:
+            if time.perf_counter() - t0 > budget_s or n >= 1000 or len(w.patches) > 1:
                 break
-            if len(w.patches) > 1 and n >= 1:
-                break
-        steps_done = max(steps_done, n)
+        nsteps = max(nsteps, n)
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    return cells / el, el, workers, steps_done, first
+    sample = (f"{w.name}: first {nsteps} step(s) of its single grid" if len(w.patches) == 1 else
+              f"{w.name}: 1 step of each of the first {pi + 1} patches")
+    cpu = {"value": cells / el, "unit": "cell-steps/s", "cores": workers, "kind": "oracle",
+           "sample": sample + f", {el:.1f} s, scipy.fft FP64 + numpy update"}
+
+    parity = {}
+    for label, (precision, gE, gB) in gpu_results.items():
+        rnd = np.float32 if precision == "fp32" else np.float64
+        per_patch = []
+        for pi, p in enumerate(w.patches):
+            E = [np.asarray(a, rnd).astype(np.float64) for a in w.E0[pi]]
+            B = [np.asarray(a, rnd).astype(np.float64) for a in w.B0[pi]]
+            if w.sources:
+                J, ro, rn = w.schedule[pi].sources(0, dtype=rnd)
+                E, B = oracle.psatd_step(E, B, [np.asarray(a, np.float64) for a in J],
+                                         np.asarray(ro, np.float64), np.asarray(rn, np.float64),
+                                         d=p.d, dt=p.dt, workers=workers)
+            else:
+                E, B = oracle.psatd_step(E, B, d=p.d, dt=steps * p.dt, workers=workers)
+            got = gE[pi] + gB[pi]
+            ref = E + B
+            per_patch.append((component_errors(got, ref, p.ndim),
+                              sum(float(np.sum((a - b) ** 2)) for a, b in zip(got, ref)),
+                              sum(float(np.sum(b * b)) for b in ref)))
+        parity[label] = summarize(per_patch)
+        parity[label]["steps"] = 1 if w.sources else steps
+        log(f"[bench]   parity {label}: {parity[label]['max_coupled_set']:.2e} (coupled set), "
+            f"{parity[label]['max_own']:.2e} (own norm), pooled {parity[label]['pooled']:.2e}")
+    return cpu, parity
+
+
+def host_fields(plan, tensors, patches):
+    """Flat device tensors -> per patch list of float64 host arrays."""
+    h = [t.detach().cpu().numpy().astype(np.float64) for t in tensors]
+    return [[x[off:off + p.cells].reshape(p.shape) for x in h]
+            for off, p in zip(plan.offsets, patches)]
 
 
 def run_fp64(pk, w, mode, cells, steps, args, vacuum_batch):
-    """The plain FP64 path on the same workload (reported beside the FP32 one)."""
+    """The plain FP64 path on the same workload (reported beside the FP32
+    one); also returns its result after the parity run (see main)."""
     import torch
 
     plan64 = pk.Plan(w.patches, precision="fp64", source_mode=mode, path="plain", graph=True,
                      autotune=True)
     E64, B64, J64, ro64, rn64 = device_fields(w, plan64, np.float64)
-    E64_1 = [t.clone() for t in E64]
-    B64_1 = [t.clone() for t in B64]
-    plan64.push(E64_1, B64_1, J64, ro64, rn64, steps=1)
+    # parity run: `steps` vacuum steps (one with sources) from the initial fields
+    Ep = [t.clone() for t in E64]
+    Bp = [t.clone() for t in B64]
+    plan64.push(Ep, Bp, J64, ro64, rn64, steps=steps if vacuum_batch else 1)
     torch.cuda.synchronize()
+    res = (host_fields(plan64, Ep, w.patches), host_fields(plan64, Bp, w.patches))
+    del Ep, Bp
     s64 = min(steps, args.fp64_steps)
     log(f"[bench] timing {s64} fp64 plain steps ...")
     sec64 = time_steps(plan64, E64, B64, J64, ro64, rn64, s64, min(args.warmup, 5), vacuum_batch)
@@ -231,9 +327,8 @@ def run_fp64(pk, w, mode, cells, steps, args, vacuum_batch):
             "steps": s64, "passes": {n: round(m, 5) for n, m in zip(plan64.pass_names, pass64)},
             "model_GBps": sum(plan64.pass_bytes) / (sec64 / s64) / 1e9}
     log(f"[bench]   fp64 plain: {fp64['ms_per_step']:.4f} ms/step")
-
     plan64.close()
-    return fp64
+    return fp64, res
 
 
 def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
@@ -368,12 +463,130 @@ def fixtures_patch(p, dt):
     return fixtures.workloads.Patch(p.ndim, p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, float(dt))
 
 
+def reap_children():
+    """End any child process this run left behind (e.g. library worker pools),
+    so that the benchmark leaves nothing running when it returns."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    for c in kids:
+        log(f"[bench] ending leftover child process {c.pid} ({c.name()})")
+        c.terminate()
+    _gone, alive = psutil.wait_procs(kids, timeout=5)
+    for c in alive:
+        c.kill()
+
+
+def pass_report(plan, pass_ms):
+    names, pbytes = plan.pass_names, plan.pass_bytes
+    grids = plan_grids(plan)
+    passes = {n: {"ms": round(m, 5), "model_GBps": round(b / (m * 1e-3) / 1e9, 1),
+                  "model_bytes": b, "grid": grids.get(n)} for n, m, b in zip(names, pass_ms, pbytes)}
+    dom = int(np.argmax(pass_ms))
+    return passes, names[dom], pbytes[dom] / (pass_ms[dom] * 1e-3) / 1e9, sum(pbytes)
+
+
+def result_line(w_name, cells, steps, args, ms_step, value, cfg, dom_name, achieved, step_bytes,
+                passes, fp64, parity, cpu):
+    traffic = measured_traffic(w_name, dom_name)
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded laser and harmonic combs; current sheet with continuity-consistent rho)",
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": dom_name},
+        "step_model_GBps": step_bytes / (ms_step * 1e-3) / 1e9,
+        "step_model_frac": step_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "passes": passes,
+        "fp64_plain": fp64,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+
+
+def bench_large_3d(pk, args, steps):
+    """Workload 4 (1024 x 1024 x 512 with sources): inputs built on the GPU
+    from the workload's seeded parameters (fixtures.device); parity and the
+    cpu_baseline on the same-seed 64^3 run."""
+    import torch
+
+    import fixtures
+    from fixtures.device import workload4_device
+
+    log("[bench] building workload 4 inputs on the GPU ...")
+    t = time.time()
+    p, E, B, J, ro, rn = workload4_device(torch)
+    torch.cuda.synchronize()
+    cells = p.cells
+    log(f"[bench]   {fixtures.CONFIG_NAMES[4]}: {cells} cells, {time.time() - t:.1f} s")
+    plan = pk.Plan([p], precision="fp32", source_mode="rho", path="fused", graph=True, autotune=True)
+    log("[bench] fp32 fused plan:\n" + plan.info)
+    log(f"[bench] timing {steps} fp32 steps (+{args.warmup} warmup) ...")
+    sec = time_steps(plan, E, B, J, ro, rn, steps, args.warmup, False)
+    ms_step = 1e3 * sec / steps
+    value = cells * steps / sec
+    log(f"[bench]   {ms_step:.4f} ms/step, {value:.4e} cell-steps/s")
+    pass_ms = plan.push_profiled(E, B, J, ro, rn, steps=min(steps, 20))
+    passes, dom_name, achieved, step_bytes = pass_report(plan, pass_ms)
+    plan.close()
+    del E, B, J, ro, rn
+    torch.cuda.empty_cache()
+    fp64 = None
+    if not args.skip_fp64:
+        p, E, B, J, ro, rn = workload4_device(torch, dtype=torch.float64)
+        plan64 = pk.Plan([p], precision="fp64", source_mode="rho", path="plain", graph=True,
+                         autotune=True)
+        s64 = min(steps, args.fp64_steps)
+        log(f"[bench] timing {s64} fp64 plain steps ...")
+        sec64 = time_steps(plan64, E, B, J, ro, rn, s64, min(args.warmup, 5), False)
+        pass64 = plan64.push_profiled(E, B, J, ro, rn, steps=min(s64, 10))
+        fp64 = {"value": cells * s64 / sec64, "unit": "cell-steps/s", "ms_per_step": 1e3 * sec64 / s64,
+                "steps": s64, "passes": {n: round(m, 5) for n, m in zip(plan64.pass_names, pass64)},
+                "model_GBps": sum(plan64.pass_bytes) / (sec64 / s64) / 1e9}
+        log(f"[bench]   fp64 plain: {fp64['ms_per_step']:.4f} ms/step")
+        plan64.close()
+        del E, B, J, ro, rn
+        torch.cuda.empty_cache()
+    cpu, parity = None, {}
+    if not args.no_cpu_baseline:
+        ws = fixtures.workload(4, shape=(64, 64, 64))
+        res = {}
+        for precision, path, dt in (("fp32", "fused", np.float32), ("fp64", "plain", np.float64)):
+            pl = pk.Plan(ws.patches, precision=precision, source_mode="rho", path=path)
+            Es, Bs, Js, ros, rns = device_fields(ws, pl, dt)
+            pl.push(Es, Bs, Js, ros, rns, steps=1)
+            torch.cuda.synchronize()
+            res[f"{precision}_{path}_64cubed_same_seed"] = (precision, host_fields(pl, Es, ws.patches),
+                                                             host_fields(pl, Bs, ws.patches))
+            pl.close()
+        log(f"[bench] oracle on host cores (~{args.cpu_budget:.0f} s budget), 64^3 same-seed run ...")
+        cpu, parity = oracle_leg(ws, args.cpu_budget, res, 1)
+    cfg = {"workload": fixtures.CONFIG_NAMES[4], "cells": cells, "patches": 1,
+           "steps_per_config": 100, "source_form": "rho", "storage": "f32", "arithmetic": "f64",
+           "path": "fused", "graph": True, "autotune": True, "inputs": "built on the GPU"}
+    out = result_line(fixtures.CONFIG_NAMES[4], cells, steps, args, ms_step, value, cfg, dom_name,
+                      achieved, step_bytes, passes, fp64, parity, cpu)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -422,23 +635,26 @@ def main():
         return bench_contrast(pk, args)
     default_steps = {0: 100, 1: 1000, 2: 200, 3: 500, 4: 100}[index]
     steps = args.steps if args.steps is not None else default_steps
+    if index == 4:
+        return bench_large_3d(pk, args, steps)
     w = build_inputs(index, steps)
     mode = "rho" if w.sources else "vacuum"
     vacuum_batch = not w.sources
     cells = w.cells
 
     # ------------------------------------------------ FP32 storage, fused path
-    # radix-4 generic line passes where every generic line is short (<= 256)
-    radix4 = max(max(p.nx // 2, p.ny) for p in w.patches) <= 256
     plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", graph=True,
-                   autotune=True, radix4_lines=radix4)
+                   autotune=True)
     log("[bench] fp32 fused plan:\n" + plan.info)
     E, B, J, ro, rn = device_fields(w, plan, np.float32)
-    # one-step parity spot check on the same inputs (before timing mutates E, B)
-    E1 = [t.clone() for t in E]
-    B1 = [t.clone() for t in B]
-    plan.push(E1, B1, J, ro, rn, steps=1)
+    # parity run of the timed configuration (the oracle leg checks it): the
+    # run's step count in vacuum, one step with sources
+    Ep = [t.clone() for t in E]
+    Bp = [t.clone() for t in B]
+    plan.push(Ep, Bp, J, ro, rn, steps=steps if vacuum_batch else 1)
     torch.cuda.synchronize()
+    res32 = (host_fields(plan, Ep, w.patches), host_fields(plan, Bp, w.patches))
+    del Ep, Bp
     log(f"[bench] timing {steps} fp32 steps (+{args.warmup} warmup) ...")
     sec = time_steps(plan, E, B, J, ro, rn, steps, args.warmup, vacuum_batch)
     ms_step = 1e3 * sec / steps
@@ -447,72 +663,39 @@ def main():
     prof_steps = min(steps, 200)
     pass_ms = plan.push_profiled(E, B, J, ro, rn, steps=prof_steps) if not vacuum_batch else \
         plan.push_profiled(E, B, steps=prof_steps)
-    names, pbytes = plan.pass_names, plan.pass_bytes
-    grids = plan_grids(plan)
-    passes = {n: {"ms": round(m, 5), "model_GBps": round(b / (m * 1e-3) / 1e9, 1),
-                  "model_bytes": b, "grid": grids.get(n)} for n, m, b in zip(names, pass_ms, pbytes)}
-    dom = int(np.argmax(pass_ms))
-    achieved = pbytes[dom] / (pass_ms[dom] * 1e-3) / 1e9
-    step_bytes = sum(pbytes)
+    passes, dom_name, achieved, step_bytes = pass_report(plan, pass_ms)
     log(f"[bench]   passes: {passes}")
-    traffic = measured_traffic(w.name, names[dom])
+    plan.close()
+    del E, B, J, ro, rn
 
     # ------------------------------------------------ FP64 storage, plain path
-    fp64 = None
+    fp64, res64 = None, None
     if not args.skip_fp64:
-        fp64 = run_fp64(pk, w, mode, cells, steps, args, vacuum_batch)
+        fp64, res64 = run_fp64(pk, w, mode, cells, steps, args, vacuum_batch)
 
-    # ------------------------------------------------ oracle: CPU baseline + parity
-    cpu = None
-    parity = {}
+    # ------------------------------------------------ oracle leg: cpu_baseline + parity
+    cpu, parity = None, {}
     if not args.no_cpu_baseline:
         log(f"[bench] oracle on host cores (~{args.cpu_budget:.0f} s budget) ...")
-        v, el, workers, nst, first = cpu_baseline(w, args.cpu_budget, np.float32)
-        sample = (f"{w.name}: first {nst} step(s) of patch 0" if len(w.patches) == 1 else
-                  f"{w.name}: 1 step of the first patches within the budget")
-        cpu = {"value": v, "unit": "cell-steps/s", "cores": workers, "kind": "oracle",
-               "sample": sample + f", {el:.1f} s, scipy.fft FP64 + numpy update"}
-        if first is not None:
-            p0 = w.patches[0]
+        results = {"fp32_fused": ("fp32",) + res32}
+        if res64 is not None:
+            results["fp64_plain"] = ("fp64",) + res64
+        cpu, parity = oracle_leg(w, args.cpu_budget, results, steps)
+        log(f"[bench]   cpu {cpu['value']:.4e} cell-steps/s on {cpu['cores']} threads")
 
-            def rel(gpuE, gpuB, plan_):
-                got = [t.detach().cpu().numpy().astype(np.float64)[:p0.cells].reshape(p0.shape)
-                       for t in gpuE + gpuB]
-                ref = first[0] + first[1]
-                return float(np.sqrt(sum(np.sum((g - r) ** 2) for g, r in zip(got, ref))
-                                     / sum(np.sum(r * r) for r in ref)))
-            parity["fp32_fused_1step_rel_l2"] = rel(E1, B1, plan)
-        log(f"[bench]   cpu {v:.4e} cell-steps/s on {workers} threads; parity {parity}")
-
-    cfg = {"workload": w.name, "cells": cells, "patches": len(w.patches), "steps_per_config": default_steps,
-           "source_form": mode, "storage": "f32", "arithmetic": "f64", "path": "fused",
-           "graph": True, "autotune": True, "radix4_lines": radix4}
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-steps/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic (seeded laser + harmonic comb, current sheet with continuity-consistent rho)",
-        "config": cfg,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": names[dom]},
-        "step_model_GBps": step_bytes / (ms_step * 1e-3) / 1e9,
-        "step_model_frac": step_bytes / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBS,
-        "passes": passes,
-        "fp64_plain": fp64,
-        "parity": parity,
-        "cpu_baseline": cpu,
-    }
-    plan.close()
+    nin = 11 if w.sources else 6
+    ws_bytes = sum(p.cells * 4 * nin * (3 if p.ndim == 3 else 2) for p in w.patches)
+    cfg = {"workload": w.name, "cells": cells, "patches": len(w.patches),
+           "steps_per_config": default_steps, "source_form": mode, "storage": "f32",
+           "arithmetic": "f64", "path": "fused", "graph": True, "autotune": True,
+           "working_set_bytes": ws_bytes}
+    out = result_line(w.name, cells, steps, args, ms_step, value, cfg, dom_name, achieved,
+                      step_bytes, passes, fp64, parity, cpu)
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    finally:
+        reap_children()

@@ -20,7 +20,9 @@ from .fields import (  # noqa: F401
     project_transverse,
     laser_2d,
     laser_3d,
+    plane_wave_list,
     plane_wave_packets_3d,
+    current_factors,
     current_profile,
     source_time_factors,
     SourceSchedule,

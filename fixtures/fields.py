@@ -177,25 +177,19 @@ def _project_separable(spec, shape, d, directions):
     return tuple(out)
 
 
-def plane_wave_packets_3d(shape, d, *, nharm, max_angle_deg, rng):
-    """Lattice plane waves n = 1..nharm, amplitude n^(-4/3), random directions.
+def plane_wave_list(shape, d, *, nharm, max_angle_deg, rng):
+    """Parameters of the lattice plane waves of :func:`plane_wave_packets_3d`.
 
-    Direction k_hat = (cos t cos p, sin p, sin t cos p) with t, p uniform in
-    [-max_angle, max_angle]; the wavevector n*k0*k_hat is snapped to the
-    nearest lattice vector, so every wave is an exact discrete Fourier mode and
-    E, B are exactly transverse without projection.  Returns (E, B, waves),
-    where ``waves`` lists (m_x, m_y, m_z, e_vec, phase) for analytic checks.
+    Returns a list of (m, e, b, phase): integer mode numbers (m_x, m_y, m_z),
+    the amplitude-scaled E and B vectors, and the phase, so that each wave is
+    E = e cos(2 pi m.x / N + phase), B = b cos(...).  Draws from ``rng`` in the
+    same order as :func:`plane_wave_packets_3d`.
     """
     nz, ny, nx = shape
     L = (nx * d[0], ny * d[1], nz * d[2])
     k0 = 2.0 * np.pi / LAMBDA0
-    x = np.arange(nx) * d[0]
-    y = np.arange(ny) * d[1]
-    z = np.arange(nz) * d[2]
-    E = [np.zeros(shape) for _ in range(3)]
-    B = [np.zeros(shape) for _ in range(3)]
-    waves = []
     lim = np.deg2rad(max_angle_deg)
+    out = []
     for n in range(1, nharm + 1):
         t, p = rng.uniform(-lim, lim, size=2)
         khat = np.array([np.cos(t) * np.cos(p), np.sin(p), np.sin(t) * np.cos(p)])
@@ -213,25 +207,50 @@ def plane_wave_packets_3d(shape, d, *, nharm, max_angle_deg, rng):
         e /= np.linalg.norm(e)
         phase = rng.uniform(0.0, 2.0 * np.pi)
         amp = n ** (-4.0 / 3.0)
+        b = np.cross(kh, e) / C_LIGHT
+        out.append((tuple(m), e * amp, b * amp, phase))
+    return out
+
+
+def plane_wave_packets_3d(shape, d, *, nharm, max_angle_deg, rng):
+    """Lattice plane waves n = 1..nharm, amplitude n^(-4/3), random directions.
+
+    Direction k_hat = (cos t cos p, sin p, sin t cos p) with t, p uniform in
+    [-max_angle, max_angle]; the wavevector n*k0*k_hat is snapped to the
+    nearest lattice vector, so every wave is an exact discrete Fourier mode and
+    E, B are exactly transverse without projection.  Returns (E, B, waves),
+    where ``waves`` lists (m_x, m_y, m_z, e_vec, phase) for analytic checks.
+    """
+    nz, ny, nx = shape
+    x = np.arange(nx) * d[0]
+    y = np.arange(ny) * d[1]
+    z = np.arange(nz) * d[2]
+    L = (nx * d[0], ny * d[1], nz * d[2])
+    E = [np.zeros(shape) for _ in range(3)]
+    B = [np.zeros(shape) for _ in range(3)]
+    waves = []
+    for m, e, b, phase in plane_wave_list(shape, d, nharm=nharm, max_angle_deg=max_angle_deg,
+                                          rng=rng):
+        kvec = [2.0 * np.pi * m[i] / L[i] for i in range(3)]
         arg = (kvec[0] * x[None, None, :] + kvec[1] * y[None, :, None]
                + kvec[2] * z[:, None, None] + phase)
-        cs = amp * np.cos(arg)
-        b = np.cross(kh, e) / C_LIGHT
+        cs = np.cos(arg)
         for i in range(3):
             E[i] += e[i] * cs
             B[i] += b[i] * cs
-        waves.append((m[0], m[1], m[2], e * amp, phase))
+        waves.append((m[0], m[1], m[2], e, phase))
     return E, B, waves
 
 
 # ---------------------------------------------------------------- sources
-def current_profile(shape, d, *, width, nmodes, min_wavelength, rng):
-    """Seeded smooth current-sheet profiles P_c = G(x) Q_c(.) and their derivatives.
+def current_factors(shape, d, *, width, nmodes, min_wavelength, rng):
+    """Separable factors of the current-sheet profiles of :func:`current_profile`.
 
-    G(x) = exp(-(x - x_c)^2 / width^2) (Gaussian in x, centred in the box);
-    Q_c is a sum of ``nmodes`` random lattice Fourier modes along the other
-    axes with wavelength >= min_wavelength.  Returns (P, D) where
-    D_c = d P_c / d x_c (spectral), so that div J = sum_c f_c(t) D_c.
+    Returns (Q, G, Gx, Qy, Qz): Q[c] of shape (nz, ny) (ny = 1 in 2D), G and
+    its spectral x derivative Gx of shape (nx,), and the spectral y derivative
+    of Q[1] and z derivative of Q[2] (Qy is zero in 2D), so that
+    P_c = Q_c G and D = (Q_0 Gx, Qy G, Qz G).  Draws from ``rng`` in the same
+    order as :func:`current_profile`.
     """
     if len(shape) == 2:
         nz, nx = shape
@@ -257,21 +276,35 @@ def current_profile(shape, d, *, width, nmodes, min_wavelength, rng):
             Q += amp * np.cos(2.0 * np.pi * (mz * z[:, None] / Lz + my * y[None, :] / Ly) + ph)
         Qs.append(Q)
 
-    def outer(q, g):
-        return q[:, 0][:, None] * g[None, :] if len(shape) == 2 else q[:, :, None] * g[None, None, :]
-
     def deriv(f, axis, n, dd):
         # spectral derivative along one axis (lattice k, Nyquist -> 0)
         k = lattice_k(n, dd).reshape([-1 if a == axis else 1 for a in range(f.ndim)])
         return np.real(sfft.ifft(1j * k * sfft.fft(f, axis=axis), axis=axis))
 
-    # P_c = Q_c(z, y) G(x) is separable, so its spectral derivative along one
-    # axis is the 1D (or 2D) derivative of the factor that depends on it
-    P = [outer(Qs[c], G) for c in range(3)]
     Gx = deriv(G, 0, nx, d[0])
-    D = [outer(Qs[0], Gx),
-         outer(deriv(Qs[1], 1, ny, d[1]), G) if len(shape) == 3 else np.zeros(shape),
-         outer(deriv(Qs[2], 0, nz, d[2]), G)]
+    Qy = deriv(Qs[1], 1, ny, d[1]) if len(shape) == 3 else np.zeros_like(Qs[1])
+    Qz = deriv(Qs[2], 0, nz, d[2])
+    return Qs, G, Gx, Qy, Qz
+
+
+def current_profile(shape, d, *, width, nmodes, min_wavelength, rng):
+    """Seeded smooth current-sheet profiles P_c = G(x) Q_c(.) and their derivatives.
+
+    G(x) = exp(-(x - x_c)^2 / width^2) (Gaussian in x, centred in the box);
+    Q_c is a sum of ``nmodes`` random lattice Fourier modes along the other
+    axes with wavelength >= min_wavelength.  Returns (P, D) where
+    D_c = d P_c / d x_c (spectral), so that div J = sum_c f_c(t) D_c.  P_c is
+    separable, so its spectral derivative along one axis is the 1D (or 2D)
+    derivative of the factor that depends on that axis.
+    """
+    Qs, G, Gx, Qy, Qz = current_factors(shape, d, width=width, nmodes=nmodes,
+                                        min_wavelength=min_wavelength, rng=rng)
+
+    def outer(q, g):
+        return q[:, 0][:, None] * g[None, :] if len(shape) == 2 else q[:, :, None] * g[None, None, :]
+
+    P = [outer(Qs[c], G) for c in range(3)]
+    D = [outer(Qs[0], Gx), outer(Qy, G) if len(shape) == 3 else np.zeros(shape), outer(Qz, G)]
     return P, D
 
 

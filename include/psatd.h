@@ -64,7 +64,12 @@ enum { PSATD_VACUUM = 0, PSATD_SOURCES_RHO = 1, PSATD_SOURCES_J = 2 }; /* update
 enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel composition */
 
 /* psatd_config.flags */
-#define PSATD_FLAG_AUTOTUNE 0x1u /* time each pass at several grid sizes at plan time (on scratch fields), keep the fastest */
+/* Time each pass alone at plan time (on scratch fields) over its candidate
+ * launch grids, tiles (lines per workgroup), modes per thread (fused pass) and,
+ * for the generic line passes, both radix schedules (PSATD_FLAG_RADIX4_LINES
+ * below or not); keep the fastest.  Grid and tile choices do not change
+ * results; the radix schedule changes them in the last bits. */
+#define PSATD_FLAG_AUTOTUNE 0x1u
 /* Capture one step into a hipGraph at plan time (or in psatd_set_workspace when
  * the plan has no workspace yet); psatd_push then writes the field pointers
  * into a plan-owned device table (one small kernel) and replays the graph
@@ -94,7 +99,9 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
  * at 8 points per thread.  Half the registers, twice the waves per SIMD:
  * faster on short lines (2D patches with sides of a few hundred cells),
  * slower on long ones.  The factorization rounds differently, so results
- * differ from the default ones in the last bits. */
+ * differ from the default ones in the last bits.  With PSATD_FLAG_AUTOTUNE
+ * both schedules are timed per pass and this flag only sets the untuned
+ * starting point. */
 #define PSATD_FLAG_RADIX4_LINES 0x40u
 
 typedef struct {

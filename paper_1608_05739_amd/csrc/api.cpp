@@ -18,6 +18,7 @@
 #include "kernels.hpp"
 #include "psatd.h"
 #include "update.hpp"
+#include "wave2d.hpp"
 
 using namespace psatd;
 
@@ -109,7 +110,8 @@ struct DeviceGuard {
   }
 };
 
-enum PassType { kLine = 0, kFused = 1, kUpdate = 2, kFastXFwd = 3, kFastZ = 4, kFastXInv = 5 };
+enum PassType { kLine = 0, kFused = 1, kUpdate = 2, kFastXFwd = 3, kFastZ = 4, kFastXInv = 5,
+                kWaveZ = 6 };
 
 struct Pass {
   PassType type;
@@ -124,6 +126,7 @@ struct Pass {
   double tuned_ms = -1.0;  // mean launch time at the chosen grid (autotune), else -1
   std::vector<int> comps;  // line passes: the components they transform
   int lines = 0;           // line passes: lines per workgroup (the tile)
+  int region = 0;          // wave-resident passes: double2 elements of LDS per wavefront
 };
 
 const char* line_pass_name(int kind) {
@@ -190,6 +193,9 @@ void free_plan_memory(psatd_plan_s* p) {
 }
 
 psatd_status hip_fail(hipError_t e, const char* what) {
+  // reset the runtime's last-error state, which the failed call set, so that
+  // it does not surface again at the caller's next, unrelated launch check
+  (void)hipGetLastError();
   return fail(e == hipErrorOutOfMemory ? PSATD_ERR_OOM : PSATD_ERR_HIP,
               std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -317,8 +323,8 @@ int line_ppt(const psatd_plan_s* plan) {
 
 // Build a line pass over all patches for the given components.
 Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
-                    std::vector<WorkItem>& items, int lines_override = 0) {
-  const int ppt = line_ppt(plan);
+                    std::vector<WorkItem>& items, int lines_override = 0, int ppt_override = 0) {
+  const int ppt = ppt_override > 0 ? ppt_override : line_ppt(plan);
   Pass ps;
   ps.type = kLine;
   ps.line_kind = kind;
@@ -492,6 +498,19 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
         return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad block size");
       continue;
     }
+    if (ps.type == kWaveZ) {
+      if (P.ndim != 2 || !wave2d::z_supported(P.nz))
+        return fail(PSATD_ERR_STATE, "z_fused (wave): z length not compiled");
+      if (w.count < 1 || w.first < 0 || w.first + w.count > P.mx ||
+          w.count > wave2d::z_lines_per_item(P.nz))
+        return fail(PSATD_ERR_STATE, "z_fused (wave): item out of range");
+      if (wave2d::z_region(P.nz) > ps.region ||
+          static_cast<size_t>(ps.region) * wave2d::kWavesPerBlock * sizeof(double2) > ps.shape.lds_bytes)
+        return fail(PSATD_ERR_STATE, "z_fused (wave): LDS region too small");
+      if (ps.shape.block != wave2d::kBlock)
+        return fail(PSATD_ERR_STATE, "z_fused (wave): bad block size");
+      continue;
+    }
     if (w.count < 1 || w.first < 0) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": empty item");
     if (ps.type == kUpdate) {
       if (static_cast<long long>(w.first) + w.count > P.comp_stride)
@@ -591,6 +610,44 @@ Pass make_fast_pass(PassType type, const psatd_plan_s* plan, const std::vector<i
   return ps;
 }
 
+// Wave-resident fused z pass (wave2d.hip): 2D, FP32 storage, the vacuum
+// forms, every z length compiled.
+bool wave_z_eligible(const psatd_plan_s* plan) {
+  const psatd_config& c = plan->cfg;
+  if (c.flags & PSATD_FLAG_GENERIC_KERNELS) return false;
+  if (plan->ndim != 2 || c.precision != PSATD_FP32 || c.path != PSATD_PATH_FUSED) return false;
+  if (plan->src_form != kVacuum && plan->src_form != kPstdVacuum) return false;
+  for (const PatchDev& P : plan->host_patches)
+    if (!wave2d::z_supported(P.nz)) return false;
+  return true;
+}
+
+// One work item per wavefront: the z lines (kx columns) one wave holds.
+Pass make_wave_z_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
+  Pass ps;
+  ps.type = kWaveZ;
+  ps.name = "z_fused";
+  const size_t first = items.size();
+  double bytes = 0.0;
+  for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+    const PatchDev& P = plan->host_patches[pi];
+    const int G = wave2d::z_lines_per_item(P.nz);
+    for (int l = 0; l < P.mx; l += G)
+      items.push_back(WorkItem{static_cast<int>(pi), l, std::min(G, P.mx - l), -1});
+    ps.region = std::max(ps.region, wave2d::z_region(P.nz));
+    ps.lines = std::max(ps.lines, G);
+    const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+    bytes += (plan->nin + 6) * cells * plan->elem;
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  const int blocks = (ps.nitems + wave2d::kWavesPerBlock - 1) / wave2d::kWavesPerBlock;
+  ps.shape = LaunchShape{blocks, wave2d::kBlock,
+                         static_cast<size_t>(ps.region) * wave2d::kWavesPerBlock * sizeof(double2)};
+  ps.bytes = bytes;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);
+  return ps;
+}
+
 psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldPtrs& f,
                           hipStream_t s) {
   hipError_t e;
@@ -607,6 +664,10 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
     case kUpdate:
       e = launch_update(plan->cfg.precision, plan->src_form, ps.shape, s, plan->d_patches,
                         ps.d_items, ps.nitems, plan->ws, ph);
+      break;
+    case kWaveZ:
+      e = wave2d::launch_z_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
+                                 ps.nitems, plan->ws, ph, ps.region);
       break;
     case kFastXFwd:
       e = fast2d::launch_x_fwd(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
@@ -788,22 +849,28 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     cands.push_back(Cand{ps, nullptr});
     // (fused passes: also at every compiled modes-per-thread choice that holds
     // the z lines; these run the same arithmetic per line)
+    // (line passes: also at both radix schedules, radix-4 stages at 4 points
+    // per thread and radices up to 8 at 8; they round differently, and each
+    // is checked against the oracle by the tests)
+    // (the wave-resident z pass: also the generic fused pass, at every choice)
     std::vector<int> vars = {0};
-    if (ps.type == kFused) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
-    if (ps.type == kLine || ps.type == kFused) {
+    if (ps.type == kFused || ps.type == kWaveZ) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
+    if (ps.type == kLine) vars = {4, kMaxPts};
+    if (ps.type == kLine || ps.type == kFused || ps.type == kWaveZ) {
       for (int m : vars) {
         if (e != hipSuccess) break;
         for (int R : {1, 2, 4, 8, 16, 32}) {
           std::vector<WorkItem> its;
           Pass c;
           if (ps.type == kLine) {
-            c = make_line_pass(ps.line_kind, plan, ps.comps, its, R);
+            c = make_line_pass(ps.line_kind, plan, ps.comps, its, R, m);
           } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
             continue;
           }
           bool seen = false;
           for (const Cand& x : cands)
-            seen = seen || (x.pass.lines == c.lines && x.pass.mpt == c.mpt && x.pass.ppt == c.ppt);
+            seen = seen || (x.pass.type == c.type && x.pass.lines == c.lines && x.pass.mpt == c.mpt &&
+                            x.pass.ppt == c.ppt);
           if (seen) continue;
           c.d_items = nullptr;
           if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
@@ -824,9 +891,12 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     double best_ms = 1e300;
     for (size_t ci = 0; ci < cands.size() && st == PSATD_OK && e == hipSuccess; ++ci) {
       Pass& c = cands[ci].pass;
-      std::vector<int> grids = {c.nitems};
+      // one workgroup per item (the wave pass: one wavefront per item), or a
+      // persistent grid of k workgroups per CU
+      const int full = c.type == kWaveZ ? c.shape.grid : c.nitems;
+      std::vector<int> grids = {full};
       for (int k : {1, 2, 4, 8})
-        if (k * plan->num_cus < c.nitems) grids.push_back(k * plan->num_cus);
+        if (k * plan->num_cus < full) grids.push_back(k * plan->num_cus);
       for (int g : grids) {
         c.shape.grid = g;
         const double ms = time_pass(c);
@@ -1013,7 +1083,9 @@ psatd_status build_plan(psatd_plan_s* plan) {
   } else {
     plan->passes.push_back(make_line_pass(kXFwd, plan, in_comps, items));
   if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYFwd, plan, in_comps, items));
-  if (cfg.path == PSATD_PATH_FUSED) {
+  if (cfg.path == PSATD_PATH_FUSED && wave_z_eligible(plan)) {
+    plan->passes.push_back(make_wave_z_pass(plan, items));
+  } else if (cfg.path == PSATD_PATH_FUSED) {
     Pass fz;
     psatd_status st = make_fused_pass(plan, items, &fz);
     if (st != PSATD_OK) return st;
@@ -1098,6 +1170,7 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
       if (!configured.count(device)) {
         hipError_t e = configure_kernel_attributes();
         if (e == hipSuccess) e = fast2d::configure_attributes();
+        if (e == hipSuccess) e = wave2d::configure_attributes();
         if (e != hipSuccess) return hip_fail(e, "kernel attributes");
         configured.insert(device);
       }

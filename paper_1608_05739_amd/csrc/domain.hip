@@ -85,6 +85,9 @@ __global__ void gather_kernel(DomainGeom G, FieldPtrs local, FieldPtrs global, i
 psatd_status fail(psatd_status s, const std::string& m) { return set_last_error(s, m); }
 
 psatd_status hip_fail(hipError_t e, const char* what) {
+  // reset the runtime's last-error state, which the failed call set, so that
+  // it does not surface again at the caller's next, unrelated launch check
+  (void)hipGetLastError();
   return fail(e == hipErrorOutOfMemory ? PSATD_ERR_OOM : PSATD_ERR_HIP,
               std::string(what) + ": " + hipGetErrorString(e));
 }

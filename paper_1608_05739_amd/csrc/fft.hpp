@@ -85,6 +85,33 @@ __device__ __forceinline__ double2 twc(double2 a) {
   else return cmul(a, make_double2(cos16(q), SIGN * sin16(q)));
 }
 
+// exp(2 pi i m / 12) from two constants (multiples of 30 degrees).
+constexpr double kH3 = 0.86602540378443865;  // sqrt(3)/2
+constexpr double cos12(int m) {
+  constexpr double t[12] = {1.0, kH3, 0.5, 0.0, -0.5, -kH3, -1.0, -kH3, -0.5, 0.0, 0.5, kH3};
+  return t[m];
+}
+constexpr double sin12(int m) {
+  constexpr double t[12] = {0.0, 0.5, kH3, 1.0, kH3, 0.5, 0.0, -0.5, -kH3, -1.0, -kH3, -0.5};
+  return t[m];
+}
+
+// a * exp(SIGN * 2 pi i M / N) for N dividing 16 or N = 12.
+template <int N, int M, int SIGN>
+__device__ __forceinline__ double2 twn(double2 a) {
+  if constexpr (16 % N == 0) {
+    return twc<N, M, SIGN>(a);
+  } else {
+    static_assert(N == 12, "compile-time twiddles for N dividing 16, or 12");
+    constexpr int m = ((M % 12) + 12) % 12;
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 3) return mul_si<SIGN>(a);
+    else if constexpr (m == 6) return make_double2(-a.x, -a.y);
+    else if constexpr (m == 9) return mul_si<-SIGN>(a);
+    else return cmul(a, make_double2(cos12(m), SIGN * sin12(m)));
+  }
+}
+
 // ------------------------------------------------------------------ small DFTs
 // In-place DFT of length R: v[k] <- sum_n v[n] exp(SIGN 2 pi i n k / R).
 template <int R, int SIGN>
@@ -138,7 +165,7 @@ __device__ __forceinline__ void dft_split(double2* x) {
     DFT<R1, SIGN>::run(t);
     static_for<0, R1>([&](auto k1c) __attribute__((always_inline)) {
       constexpr int k1 = decltype(k1c)::value;
-      a[n2][k1] = twc<N, n2 * k1, SIGN>(t[k1]);
+      a[n2][k1] = twn<N, n2 * k1, SIGN>(t[k1]);
     });
   });
 #pragma unroll
@@ -160,6 +187,11 @@ struct DFT<8, SIGN> {
 template <int SIGN>
 struct DFT<16, SIGN> {
   static __device__ __forceinline__ void run(double2* v) { dft_split<4, 4, SIGN>(v); }
+};
+
+template <int SIGN>
+struct DFT<12, SIGN> {
+  static __device__ __forceinline__ void run(double2* v) { dft_split<4, 3, SIGN>(v); }
 };
 
 // ------------------------------------------------------------------ LDS layout and indices

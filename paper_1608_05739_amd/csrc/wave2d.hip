@@ -1,0 +1,184 @@
+// Wave-resident kernels for batched 2D patches (FP32 storage, FP64
+// arithmetic).
+//
+// Fused z pass: one wavefront per work item, which is a group of G kx columns
+// (z lines of length L = nz, G = 64 / (L / P)) of one patch.  For each
+// polarization group (s: Ey, Bx, Bz; p: Ex, Ez, By, with their sources) the
+// wave loads every input's lines (lane s of line g holds z = s + S m), runs
+// the forward FFT of each in registers with exchanges through its own LDS
+// region (wfft.hpp), updates every mode, and runs the inverse FFT of each
+// output.  No workgroup barrier: the waves of a block work on their own
+// items.  The spectra keep the layout of the generic kernels ([kx][z], FP32,
+// column 0 carrying the DC and Nyquist columns packed; both have kx = 0), so
+// these passes combine with the generic x passes.
+#include <hip/hip_runtime.h>
+
+#include "groups.hpp"
+#include "update.hpp"
+#include "wave2d.hpp"
+#include "wfft.hpp"
+
+namespace psatd {
+namespace wave2d {
+
+__device__ __forceinline__ double2 f2d(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ float2 d2f(double2 v) {
+  return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+
+template <int L, int SRC, int GR>
+__device__ __forceinline__ void z_group(const PatchDev* P, const WorkItem& wi, float* ws,
+                                        const Physics& ph, double2* region, int lane) {
+  using LN = wfft::Line<L>;
+  using Gr = Group<GR, SRC>;
+  constexpr int NP = LN::P;
+  constexpr int S = LN::S;
+  constexpr int NIN = Gr::nin;
+  const int g = lane / S;
+  const int s = lane % S;
+  const bool active = g < wi.count;
+  const int line = wi.first + (active ? g : 0);
+  // wave-uniform base of the item's first line (scalar registers) and the
+  // lane's 32-bit element offset, so that loads and stores address as
+  // scalar base + lane offset + immediate
+  float2* const base = reinterpret_cast<float2*>(ws) + P->off_z + static_cast<long long>(wi.first) * L;
+  const int loff = (active ? g : 0) * L + s;
+  const long long cs = P->comp_stride;
+  const double2* tw = P->fz.tw;
+
+  // forward transforms of the group's inputs, kept in FP32 until the update
+  float2 held[NIN][NP];
+  static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+    constexpr int slot = decltype(sc)::value;
+    const float2* src = base + Gr::in[slot] * cs;
+    double2 v[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) v[m] = f2d(src[loff + S * m]);  // inactive lanes: a valid line
+    wfft::fft<L, -1>(v, region, g, s, tw);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) held[slot][m] = d2f(v[m]);
+  });
+
+  // per-mode update (kx of the line, kz of mode s + S m)
+  const double kx = gload(P->kx, line);
+  const double dt = P->dt;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const double kz = gload(P->kz, s + S * m);
+    double2 E[3] = {}, B[3] = {}, J[3] = {};
+    double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+    static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int slot = decltype(sc)::value;
+      constexpr int comp = Gr::in[slot];
+      const double2 v = f2d(held[slot][m]);
+      if constexpr (comp < 3) E[comp] = v;
+      else if constexpr (comp < 6) B[comp - 3] = v;
+      else if constexpr (comp < 9) J[comp - 6] = v;
+      else if constexpr (comp == kRhoOld) ro = v;
+      else rn = v;
+    });
+    double2 Eo[3], Bo[3];
+    if constexpr (src_is_pstd(SRC)) {
+      pstd_update_mode<SRC>(kx, 0.0, kz, dt, ph.c, ph.eps0, P->inv_n, E, B, J, Eo, Bo);
+    } else {
+      const double K = sqrt(kx * kx + kz * kz);
+      const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
+      update_mode<SRC>(kx, 0.0, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+    }
+    static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
+      constexpr int o = decltype(oc)::value;
+      constexpr int comp = Gr::in[Gr::out_slot[o]];
+      if constexpr (comp < 3) held[Gr::out_slot[o]][m] = d2f(Eo[comp]);
+      else held[Gr::out_slot[o]][m] = d2f(Bo[comp - 3]);
+    });
+    // keep the modes' updates from being interleaved (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // inverse transforms of the outputs, written over their inputs
+  static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
+    constexpr int o = decltype(oc)::value;
+    constexpr int slot = Gr::out_slot[o];
+    double2 v[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) v[m] = f2d(held[slot][m]);
+    wfft::fft<L, 1>(v, region, g, s, tw);
+    if (active) {
+      float2* dst = base + Gr::in[slot] * cs;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) dst[loff + S * m] = d2f(v[m]);
+    }
+  });
+}
+
+template <int L, int SRC>
+__device__ __forceinline__ void z_item(const PatchDev* P, const WorkItem& wi, float* ws,
+                                       const Physics& ph, double2* region, int lane) {
+  z_group<L, SRC, 0>(P, wi, ws, ph, region, lane);
+  z_group<L, SRC, 1>(P, wi, ws, ph, region, lane);
+}
+
+template <int SRC>
+__global__ void __launch_bounds__(kBlock)
+wave_z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
+                    int nitems, float* __restrict__ ws, Physics ph, int region_elems) {
+  extern __shared__ double2 lds[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double2* region = lds + wave * region_elems;
+  for (int it = blockIdx.x * kWavesPerBlock + wave; it < nitems; it += gridDim.x * kWavesPerBlock) {
+    const WorkItem wi = items[it];
+    const PatchDev* P = patches + wi.patch;
+    switch (P->nz) {
+      case 32: z_item<32, SRC>(P, wi, ws, ph, region, lane); break;
+      case 48: z_item<48, SRC>(P, wi, ws, ph, region, lane); break;
+      case 64: z_item<64, SRC>(P, wi, ws, ph, region, lane); break;
+      case 96: z_item<96, SRC>(P, wi, ws, ph, region, lane); break;
+      case 128: z_item<128, SRC>(P, wi, ws, ph, region, lane); break;
+      case 192: z_item<192, SRC>(P, wi, ws, ph, region, lane); break;
+      case 256: z_item<256, SRC>(P, wi, ws, ph, region, lane); break;
+      case 384: z_item<384, SRC>(P, wi, ws, ph, region, lane); break;
+      default: z_item<512, SRC>(P, wi, ws, ph, region, lane); break;
+    }
+  }
+}
+
+bool z_supported(int nz) {
+  return nz == 32 || nz == 48 || nz == 64 || nz == 96 || nz == 128 || nz == 192 || nz == 256 ||
+         nz == 384 || nz == 512;
+}
+
+int z_lines_per_item(int nz) { return 64 / (nz / wfft::points(nz)); }
+
+int z_region(int nz) { return z_lines_per_item(nz) * (nz + nz / 8); }
+
+hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
+                          const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
+                          Physics ph, int region) {
+  float* w = static_cast<float*>(ws);
+  switch (src) {
+    case kVacuum:
+      hipLaunchKernelGGL((wave_z_fused_kernel<kVacuum>), dim3(sh.grid), dim3(kBlock), sh.lds_bytes,
+                         stream, patches, items, nitems, w, ph, region);
+      break;
+    case kPstdVacuum:
+      hipLaunchKernelGGL((wave_z_fused_kernel<kPstdVacuum>), dim3(sh.grid), dim3(kBlock),
+                         sh.lds_bytes, stream, patches, items, nitems, w, ph, region);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t configure_attributes() {
+  const int lim = 160 * 1024;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&wave_z_fused_kernel<kVacuum>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&wave_z_fused_kernel<kPstdVacuum>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  return e != hipSuccess ? e : r;
+}
+
+}  // namespace wave2d
+}  // namespace psatd

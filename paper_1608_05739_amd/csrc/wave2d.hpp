@@ -1,0 +1,32 @@
+// Wave-resident 2D kernels (wave2d.hip): launchers and the lengths they take.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace psatd {
+namespace wave2d {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = 64 * kWavesPerBlock;
+
+// z line lengths the fused z pass is compiled for.
+bool z_supported(int nz);
+// z lines of one work item (one wavefront): 64 / (lanes per line).
+int z_lines_per_item(int nz);
+// double2 elements of one wavefront's LDS region for z lines of length nz.
+int z_region(int nz);
+
+// Fused z pass over 2D patches stored as FP32 [kx][z] spectra: per work item
+// one wavefront transforms `count` z lines of every input along z, updates
+// each mode and transforms E', B' back.  region = double2 elements per wave.
+hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
+                          const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
+                          Physics ph, int region);
+
+hipError_t configure_attributes();
+
+}  // namespace wave2d
+}  // namespace psatd

@@ -70,3 +70,24 @@ def test_plan_grids_parses_the_plan_info():
     p = P()
     p.info = info
     assert bench.plan_grids(p) == {"x_r2c_fwd": 5632, "z_fused": 256}
+
+
+def test_kernel_names_map_to_passes():
+    assert bench.pass_of_kernel("void psatd::line_pass_kernel<float, 0, 4>(psatd::PatchDev const*)") == "x_r2c_fwd"
+    assert bench.pass_of_kernel("void psatd::line_pass_kernel<float, 3, 8>(...)") == "y_c2c_inv"
+    assert bench.pass_of_kernel("void psatd::fused_z_kernel<float, 2, 0, 2>(...)") == "z_fused"
+    assert bench.pass_of_kernel("psatd::fast2d::z_fused_kernel<1, true>(...)") == "z_fused"
+    assert bench.pass_of_kernel("__amd_rocclr_copyBuffer") is None
+
+
+def test_component_errors_use_coupled_sets():
+    import numpy as np
+    rng = np.random.default_rng(0)
+    ref = [rng.normal(size=(8, 8)) * s for s in (1, 1e-3, 1, 1e-3, 1, 1e-3)]
+    got = [r.copy() for r in ref]
+    got[5] = got[5] * (1 + 1e-2)
+    e = bench.component_errors(got, ref, 2)
+    assert e["Bz"][0] > 5e-3 and e["Bz"][1] > 5e-3  # the s set is small as a whole
+    assert e["Ex"] == (0.0, 0.0)
+    e3 = bench.component_errors(got, ref, 3)
+    assert e3["Bz"][1] < 1e-4  # in 3D the set is all six components

@@ -209,3 +209,17 @@ def test_workspace_beyond_device_memory_reports_oom():
     assert ei.value.status == -3
     torch.cuda.synchronize()
     assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)
+
+
+def test_plans_work_after_an_out_of_memory_plan():
+    """After a plan fails with PSATD_ERR_OOM the runtime's error state is
+    clear: the next plan and push succeed."""
+    import torch
+    with pytest.raises(pk.PsatdError):
+        pk.Plan([pk.Patch(3, (2048, 1024, 1024), (0.1, 0.1, 0.1), 0.05, offset=o)
+                 for o in (0, 2048 * 1024 * 1024)], precision="fp32", source_mode="rho")
+    plan = pk.Plan([_patch()])
+    E, B = (_fields(plan.total_elements, torch.float32) for _ in range(2))
+    plan.push(E, B, steps=2)
+    torch.cuda.synchronize()
+    plan.close()
