@@ -10,9 +10,12 @@ Contents
   psatd       k tables, PSATD coefficients, the per-mode update (rho-form and
               J-form) and the full step (r2c or c2c transforms), written from
               Sec. III.B item 2 and Table 1 (PSATD row).
-  dispersion  refractive-index formulas of Table 1, the Snell-Descartes
-              refraction model of Sec. IV (eq. 1) and a CPU Yee FDTD stepper,
-              used only as the contrast the paper draws against PSATD.
+  dispersion  refractive-index formulas of Table 1, the order-p stencils,
+              Appendix A and a CPU Yee FDTD stepper, used only as the
+              contrast the paper draws against PSATD.
+  refraction  the Snell-Descartes refraction model of Sec. IV (eq. 1): each
+              solver's index n_r(omega, theta), the Newton-Raphson solve for
+              theta_r(omega), and the index maps of Fig. 2.
   contrast    the contrast solvers as full field steps (Sec. III.A, Table 1):
               Yee and order-p FDTD on the staggered grid, CKC, and PSTD.
   decomposition  the guard-cell domain decomposition (Sec. II.A).

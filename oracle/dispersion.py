@@ -22,6 +22,7 @@ Readings of garbled or inconsistent printed formulas:
 
 from __future__ import annotations
 
+import functools
 from fractions import Fraction
 
 import numpy as np
@@ -116,6 +117,13 @@ def fornberg_centered(p: int):
     return weights
 
 
+@functools.lru_cache(maxsize=None)
+def _float_weights(p: int, stencil: str):
+    """The order-p weights as floats (computed once per order and stencil)."""
+    w = fornberg_staggered(p) if stencil == "staggered" else fornberg_centered(p)
+    return tuple(float(x) for x in w)
+
+
 def modified_k(k, dx, p: int, stencil: str = "staggered"):
     """Wavenumber of the order-p first-derivative stencil; p = 0 returns k.
 
@@ -126,15 +134,12 @@ def modified_k(k, dx, p: int, stencil: str = "staggered"):
     k = np.asarray(k, dtype=np.float64)
     if p == 0:
         return k.copy()
-    out = np.zeros_like(k)
-    if stencil == "staggered":
-        for l, cl in enumerate(fornberg_staggered(p), start=1):
-            out += float(cl) * (2.0 / dx) * np.sin((2 * l - 1) * k * dx / 2.0)
-    elif stencil == "centered":
-        for l, al in enumerate(fornberg_centered(p), start=1):
-            out += float(al) * (2.0 / dx) * np.sin(l * k * dx)
-    else:
+    if stencil not in ("staggered", "centered"):
         raise ValueError(f"unknown stencil {stencil!r}")
+    out = np.zeros_like(k)
+    for l, wl in enumerate(_float_weights(p, stencil), start=1):
+        arg = (2 * l - 1) * k * dx / 2.0 if stencil == "staggered" else l * k * dx
+        out += wl * (2.0 / dx) * np.sin(arg)
     return out
 
 

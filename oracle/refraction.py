@@ -67,37 +67,33 @@ def _k_edge(theta, dx, dz):
 def index_at(solver, omega, theta, dx, dz, dt, c=1.0, order=0, stencil="staggered"):
     """n_r(omega, theta) = c |k| / omega for the mode of frequency omega
     propagating along theta (NaN if there is none)."""
+    if not np.isfinite(theta):
+        return np.nan
     ct, st = np.cos(theta), np.sin(theta)
+    hi = _k_edge(theta, dx, dz)
+    # the dispersion branch rises from 0 along the direction; keep the part
+    # where it still rises (and is defined), so the root is bracketed and unique
+    ks = np.linspace(0.0, hi, 513)
+    w = np.asarray(omega_num(solver, ks * ct, ks * st, dx, dz, dt, c, order, stencil), float)
+    stop = np.nonzero(~np.isfinite(w[1:]) | (np.diff(w) < 0.0))[0]
+    top = int(stop[0]) if stop.size else len(ks) - 1
+    if not w[top] >= omega:
+        return np.nan
+    i = max(int(np.searchsorted(w[: top + 1], omega)), 1)
+    lo, hi = ks[i - 1], ks[i]
 
     def f(k):
         return float(omega_num(solver, k * ct, k * st, dx, dz, dt, c, order, stencil)) - omega
 
-    lo, hi = 0.0, _k_edge(theta, dx, dz)
-    # the dispersion branch rises from 0; keep the part where it still rises
-    # (and is defined) so that the root is bracketed and unique
-    n = 256
-    ks = np.linspace(lo, hi, n + 1)
-    w = np.array([f(k) for k in ks]) + omega
-    ok = np.isfinite(w)
-    w_max_i = 0
-    for i in range(1, n + 1):
-        if not ok[i] or w[i] < w[i - 1]:
-            break
-        w_max_i = i
-    if w[w_max_i] < omega:
-        return np.nan
-    i = int(np.searchsorted(w[: w_max_i + 1], omega))
-    lo, hi = ks[max(i - 1, 0)], ks[i]
-    for _ in range(200):  # bisection to a tight bracket
+    for _ in range(80):  # bisection within the bracket
         mid = 0.5 * (lo + hi)
         if f(mid) < 0.0:
             lo = mid
         else:
             hi = mid
-        if hi - lo <= 1e-15 * hi:
+        if hi - lo <= 4e-16 * hi:
             break
-    k = 0.5 * (lo + hi)
-    return c * k / omega
+    return c * 0.5 * (lo + hi) / omega
 
 
 def refraction_angle(solver, omega, theta_i, dx, dz, dt, c=1.0, n_i=1.0, order=0,
@@ -131,3 +127,15 @@ def refraction_angle(solver, omega, theta_i, dx, dz, dt, c=1.0, n_i=1.0, order=0
         if abs(step) <= 1e-16:
             return th if abs(g(th)) <= 1e-12 else np.nan
     return th if abs(g(th)) <= 1e-12 else np.nan
+
+
+def index_map(solver, eta, kdx, theta, dx=1.0, c=1.0, order=0, stencil="staggered"):
+    """Refractive-index map of Fig. 2: n = c |k| / omega_num(k) on the grid of
+    wavenumbers |k| dx = ``kdx`` (1D array) and directions ``theta`` (1D
+    array, radians from the x axis), at Courant number eta = c dt / dx (square
+    cells).  Returns an array [len(theta), len(kdx)]; NaN where the scheme has
+    no stable mode."""
+    K, T = np.meshgrid(np.asarray(kdx, float) / dx, np.asarray(theta, float))
+    w = omega_num(solver, K * np.cos(T), K * np.sin(T), dx, dx, eta * dx / c, c, order, stencil)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(K > 0, c * K / w, 1.0)
