@@ -61,7 +61,13 @@ typedef enum {
 
 enum { PSATD_FP32 = 0, PSATD_FP64 = 1 };                               /* field element type */
 enum { PSATD_VACUUM = 0, PSATD_SOURCES_RHO = 1, PSATD_SOURCES_J = 2 }; /* update form        */
-enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel composition */
+/* Kernel composition.  PLAIN: separate z transforms and a per-mode update
+ * pass.  FUSED: one pass runs the forward z transforms, the update and the
+ * inverse z transforms of whole z lines in a workgroup; where the z lines of
+ * the plan are too long for one workgroup (nz above 4096 FP32 2D, 2048 FP64
+ * 2D or FP32 3D, 1024 FP64 3D) it runs the plain z passes instead.  Same
+ * results up to rounding either way. */
+enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };
 
 /* psatd_config.flags */
 /* Time each pass alone at plan time (on scratch fields) over its candidate
@@ -101,7 +107,8 @@ enum { PSATD_PATH_FUSED = 0, PSATD_PATH_PLAIN = 1 };                   /* kernel
  * slower on long ones.  The factorization rounds differently, so results
  * differ from the default ones in the last bits.  With PSATD_FLAG_AUTOTUNE
  * both schedules are timed per pass and this flag only sets the untuned
- * starting point. */
+ * starting point.  A pass with a line longer than 2048 points keeps the
+ * default schedule (512 threads at 4 points hold no more). */
 #define PSATD_FLAG_RADIX4_LINES 0x40u
 
 typedef struct {
@@ -140,6 +147,17 @@ typedef struct {
  * once.  *out is set only on success. */
 psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches,
                         int32_t npatches, int32_t device, psatd_plan_t* out);
+
+/* Host-only planning: the same validation, workspace layout, pass and
+ * work-list construction and work-list verification as psatd_plan, with no
+ * HIP call and no device memory (the autotune and graph flags are ignored:
+ * both need a device).  On success *ws_bytes (if not NULL) is the workspace
+ * psatd_plan would allocate and info (if not NULL) holds the pass description
+ * psatd_plan_info would give before autotuning, NUL-terminated and truncated
+ * to len.  Errors are the ones psatd_plan returns for the same arguments.
+ * Safe to call without a GPU; used to check the planner on the CPU. */
+psatd_status psatd_plan_describe(const psatd_config* cfg, const psatd_patch_desc* patches,
+                                 int32_t npatches, size_t* ws_bytes, char* info, size_t len);
 
 /* Bytes of device workspace the plan needs: the k-space spectra of all inputs
  * (twice that in 3D, where the y passes move them between two blocks). */

@@ -14,5 +14,6 @@ from ._binding import (  # noqa: F401
     Plan,
     PsatdError,
     as_patch,
+    describe_plan,
     load_library,
 )

@@ -39,6 +39,7 @@ EXPORTED_SYMBOLS = (
     "psatd_plan_info", "psatd_destroy", "psatd_status_string", "psatd_last_error",
     "psatd_domain_create", "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
     "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy",
+    "psatd_plan_describe",
 )
 
 
@@ -91,6 +92,8 @@ def load_library(path: Optional[str] = None):
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     lib.psatd_plan.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(PatchDesc), i32, i32,
                                ctypes.POINTER(vp)]
+    lib.psatd_plan_describe.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(PatchDesc), i32,
+                                        ctypes.POINTER(sz), ctypes.c_char_p, sz]
     lib.psatd_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.psatd_set_workspace.argtypes = [vp, vp, sz]
     lib.psatd_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
@@ -116,7 +119,7 @@ def load_library(path: Optional[str] = None):
                                     ctypes.POINTER(vp)]
     lib.psatd_fdtd_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
     lib.psatd_fdtd_destroy.argtypes = [vp]
-    for name in ("psatd_plan", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
+    for name in ("psatd_plan", "psatd_plan_describe", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
                  "psatd_push_profiled", "psatd_pass_count", "psatd_pass_bytes",
                  "psatd_plan_info", "psatd_destroy", "psatd_domain_create",
                  "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
@@ -208,6 +211,47 @@ def _field_struct(E, B, J, rho_old, rho_new, want_dtype, min_elements):
     return f
 
 
+def _patch_descs(patches):
+    """(patches, PatchDesc array, offsets, total elements); patches without an
+    offset are packed in order, each padded to an even element count."""
+    ps = [as_patch(p) for p in patches]
+    off = 0
+    offsets = []
+    for p in ps:
+        if p.offset is None:
+            offsets.append(off)
+            off += p.cells + (p.cells % 2)
+        else:
+            offsets.append(int(p.offset))
+            off = max(off, int(p.offset) + p.cells)
+    descs = (PatchDesc * max(1, len(ps)))()
+    for i, p in enumerate(ps):
+        descs[i].ndim = p.ndim
+        descs[i].n = (ctypes.c_int64 * 3)(*[int(v) for v in p.n])
+        descs[i].d = (ctypes.c_double * 3)(*[float(v) for v in p.d])
+        descs[i].dt = float(p.dt)
+        descs[i].offset = offsets[i]
+    return ps, descs, offsets, off
+
+
+def describe_plan(patches: Sequence, *, precision="fp32", source_mode="vacuum", path="fused",
+                  order=0, c=1.0, eps0=1.0, generic_kernels=False, centered_stencil=False,
+                  pstd=False, radix4_lines=False):
+    """Plan on the host only (psatd_plan_describe): validates and lays out the
+    plan without touching a device.  Returns (workspace bytes, pass
+    description); raises PsatdError where Plan() would."""
+    lib = load_library()
+    ps, descs, _, _ = _patch_descs(patches)
+    cfg = make_config(precision, source_mode, path, order, c, eps0,
+                      generic_kernels=generic_kernels, centered_stencil=centered_stencil,
+                      pstd=pstd, radix4_lines=radix4_lines)
+    ws = ctypes.c_size_t()
+    buf = ctypes.create_string_buffer(16384)
+    _check(lib, lib.psatd_plan_describe(ctypes.byref(cfg), descs, len(ps), ctypes.byref(ws),
+                                        buf, len(buf)))
+    return ws.value, buf.value.decode()
+
+
 class Plan:
     """A PSATD plan over one or more periodic patches on one HIP device.
 
@@ -224,28 +268,11 @@ class Plan:
                  centered_stencil=False, pstd=False, radix4_lines=False):
         self._lib = load_library()
         self._plan = None
-        ps = [as_patch(p) for p in patches]
-        off = 0
-        self.offsets = []
-        for p in ps:
-            if p.offset is None:
-                self.offsets.append(off)
-                off += p.cells + (p.cells % 2)
-            else:
-                self.offsets.append(int(p.offset))
-                off = max(off, int(p.offset) + p.cells)
-        self.total_elements = off
+        ps, descs, self.offsets, self.total_elements = _patch_descs(patches)
         self.patches = ps
         self.precision = precision
         self.source_mode = source_mode
         self.device = device
-        descs = (PatchDesc * len(ps))()
-        for i, p in enumerate(ps):
-            descs[i].ndim = p.ndim
-            descs[i].n = (ctypes.c_int64 * 3)(*[int(v) for v in p.n])
-            descs[i].d = (ctypes.c_double * 3)(*[float(v) for v in p.d])
-            descs[i].dt = float(p.dt)
-            descs[i].offset = self.offsets[i]
         cfg = make_config(precision, source_mode, path, order, c, eps0, autotune=autotune,
                           graph=graph, allocate_workspace=allocate_workspace,
                           generic_kernels=generic_kernels, centered_stencil=centered_stencil,

@@ -113,6 +113,14 @@ struct DeviceGuard {
 enum PassType { kLine = 0, kFused = 1, kUpdate = 2, kFastXFwd = 3, kFastZ = 4, kFastXInv = 5,
                 kWaveZ = 6 };
 
+// One launch of a compile-time line pass: the work items of one line length.
+struct SubLaunch {
+  int L = 0;
+  int first = 0;  // index of its first work item within the pass's list
+  int nitems = 0;
+  LaunchShape shape{};
+};
+
 struct Pass {
   PassType type;
   int line_kind;
@@ -127,6 +135,8 @@ struct Pass {
   std::vector<int> comps;  // line passes: the components they transform
   int lines = 0;           // line passes: lines per workgroup (the tile)
   int region = 0;          // wave-resident passes: double2 elements of LDS per wavefront
+  bool ct = false;         // line passes: the compile-time-length kernels (ct_line_kernel),
+  std::vector<SubLaunch> subs;  // one launch per line length
 };
 
 const char* line_pass_name(int kind) {
@@ -167,6 +177,10 @@ struct psatd_plan_s {
   hipGraph_t graph = nullptr;
   FieldPtrs* d_fieldtab = nullptr;  // field pointers the graph's kernels read (FieldPtrs::table)
   std::string info;
+  // host-only planning (psatd_plan_describe): no device call is made, the
+  // table addresses point into this host block and are never dereferenced
+  bool dry = false;
+  std::vector<char> dry_tables;
 };
 
 namespace {
@@ -322,9 +336,99 @@ int line_ppt(const psatd_plan_s* plan) {
 }
 
 // Build a line pass over all patches for the given components.
+// The compile-time line kernels take every patch of the plan if each line
+// length is compiled and no tile would straddle a multiple of the tile map's A
+// (the strided side of x and y passes; one division per tile places it).
+bool ct_line_eligible(int kind, const psatd_plan_s* plan) {
+  // (PSATD_FLAG_RADIX4_LINES asks for the generic radix-4 schedule)
+  if (plan->cfg.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
+  for (const PatchDev& P : plan->host_patches) {
+    int nlines, L;
+    line_geometry(kind, P, &nlines, &L);
+    if (!ct_line_supported(L)) return false;
+    const int R = std::min(ct_line_tile(L), nlines);
+    int A = 0;
+    if (kind == kXFwd || kind == kXInv) A = P.ndim == 2 ? P.nz : P.ny;
+    if (kind == kYFwd || kind == kYInv) A = P.nz;
+    if (A > 0 && (R > A || A % R != 0)) return false;
+  }
+  return true;
+}
+
+Pass make_ct_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
+                       std::vector<WorkItem>& items) {
+  Pass ps;
+  ps.type = kLine;
+  ps.ct = true;
+  ps.line_kind = kind;
+  ps.ppt = 0;
+  ps.name = line_pass_name(kind);
+  size_t lds = 0;
+  const size_t first = items.size();
+  double bytes = 0.0;
+  std::set<int> lengths;
+  for (const PatchDev& P : plan->host_patches) {
+    int nlines, L;
+    line_geometry(kind, P, &nlines, &L);
+    lengths.insert(L);
+  }
+  for (int Lc : lengths) {
+    SubLaunch sub;
+    sub.L = Lc;
+    sub.first = static_cast<int>(items.size() - first);
+    for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+      const PatchDev& P = plan->host_patches[pi];
+      int nlines, L;
+      line_geometry(kind, P, &nlines, &L);
+      if (L != Lc) continue;
+      const int R = std::min(ct_line_tile(L), nlines);
+      ps.lines = std::max(ps.lines, R);
+      for (int c : comps)
+        for (int l = 0; l < nlines; l += R)
+          items.push_back(WorkItem{static_cast<int>(pi), l, std::min(R, nlines - l), c});
+      const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+      bytes += comps.size() * 2.0 * cells * plan->elem;
+    }
+    sub.nitems = static_cast<int>(items.size() - first) - sub.first;
+    const size_t sub_lds = static_cast<size_t>(lpad_size(ct_line_tile(Lc) * Lc)) * sizeof(double2);
+    sub.shape = LaunchShape{sub.nitems, kCtBlock, sub_lds};
+    lds = std::max(lds, sub_lds);
+    ps.subs.push_back(sub);
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  ps.shape = LaunchShape{ps.nitems, kCtBlock, lds};
+  ps.bytes = bytes;
+  ps.comps = comps;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);
+  return ps;
+}
+
+// Launch grid of a pass: g workgroups, or for the compile-time line passes
+// (one launch per length) g = 0 for one workgroup per item and g = k for at
+// most k workgroups per CU in each launch.
+void set_grid(const psatd_plan_s* plan, Pass& ps, int g) {
+  if (!ps.ct) {
+    ps.shape.grid = g;
+    return;
+  }
+  int total = 0;
+  for (SubLaunch& sub : ps.subs) {
+    sub.shape.grid = g == 0 ? sub.nitems : std::min(sub.nitems, g * plan->num_cus);
+    total += sub.shape.grid;
+  }
+  ps.shape.grid = total;
+}
+
 Pass make_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
                     std::vector<WorkItem>& items, int lines_override = 0, int ppt_override = 0) {
-  const int ppt = ppt_override > 0 ? ppt_override : line_ppt(plan);
+  int ppt = ppt_override > 0 ? ppt_override : line_ppt(plan);
+  // a line longer than the threads of a workgroup can hold at this many
+  // points each runs at the default points per thread
+  for (const PatchDev& P : plan->host_patches) {
+    int nlines, L;
+    line_geometry(kind, P, &nlines, &L);
+    if (L > kLineBlockMax * points_per_thread(L, ppt)) ppt = kMaxPts;
+  }
   Pass ps;
   ps.type = kLine;
   ps.line_kind = kind;
@@ -450,6 +554,19 @@ psatd_status make_fused_pass(const psatd_plan_s* plan, std::vector<WorkItem>& it
   return st;
 }
 
+// Does the fused pass hold every patch's z lines at some compiled choice?
+// (Longer lines run as the plain z passes instead: transform, update,
+// transform.)  Leaves items and the last error as they were.
+bool fused_fits(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
+  const size_t n0 = items.size();
+  const std::string before = g_last_error;
+  Pass probe;
+  const bool ok = make_fused_pass(plan, items, &probe) == PSATD_OK;
+  items.resize(n0);
+  g_last_error = before;
+  return ok;
+}
+
 Pass make_update_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
   Pass ps;
   ps.type = kUpdate;
@@ -479,7 +596,7 @@ Pass make_update_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
 // within the per-thread register budget.
 psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkItem* items) {
   const int maxpts = ps.type == kFused ? kMaxPtsFused : ps.ppt;
-  if (ps.type == kLine && !line_ppt_supported(ps.ppt))
+  if (ps.type == kLine && !ps.ct && !line_ppt_supported(ps.ppt))
     return fail(PSATD_ERR_STATE, std::string(ps.name) + ": points per thread not compiled");
   for (int i = 0; i < ps.nitems; ++i) {
     const WorkItem& w = items[i];
@@ -515,6 +632,30 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
     if (ps.type == kUpdate) {
       if (static_cast<long long>(w.first) + w.count > P.comp_stride)
         return fail(PSATD_ERR_STATE, "update: item past the spectrum");
+      continue;
+    }
+    if (ps.type == kLine && ps.ct) {
+      int nlines, L;
+      line_geometry(ps.line_kind, P, &nlines, &L);
+      bool in_sub = false;
+      for (const SubLaunch& sub : ps.subs)
+        in_sub = in_sub || (i >= sub.first && i < sub.first + sub.nitems && sub.L == L &&
+                            sub.shape.lds_bytes >= static_cast<size_t>(lpad_size(ct_line_tile(L) * L)) *
+                                                       sizeof(double2));
+      if (!in_sub) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item outside its length's launch");
+      if (!ct_line_supported(L)) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": length not compiled");
+      if (w.comp < 0 || w.comp >= plan->nin)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad component");
+      if (w.count < 1 || w.first < 0 || w.first + w.count > nlines || w.count > ct_line_tile(L))
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item out of range");
+      int A = 0;
+      if (ps.line_kind == kXFwd || ps.line_kind == kXInv) A = P.ndim == 2 ? P.nz : P.ny;
+      if (ps.line_kind == kYFwd || ps.line_kind == kYInv) A = P.nz;
+      if (A > 0 && w.first / A != (w.first + w.count - 1) / A)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": tile straddles the tile map");
+      if (static_cast<size_t>(lpad_size(ct_line_tile(L) * L)) * sizeof(double2) > ps.shape.lds_bytes)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item exceeds LDS");
+      if (ps.shape.block != kCtBlock) return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad block size");
       continue;
     }
     int nlines, L;
@@ -649,35 +790,44 @@ Pass make_wave_z_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
 }
 
 psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldPtrs& f,
-                          hipStream_t s) {
+                          hipStream_t s, void* ws) {
   hipError_t e;
   const Physics ph{plan->cfg.c, plan->cfg.eps0};
   switch (ps.type) {
     case kLine:
-      e = launch_line_pass(ps.line_kind, plan->cfg.precision, ps.ppt, ps.shape, s,
-                           plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
+      if (ps.ct) {
+        e = hipSuccess;
+        for (const SubLaunch& sub : ps.subs) {
+          e = launch_ct_line(ps.line_kind, plan->cfg.precision, sub.L, sub.shape, s,
+                             plan->d_patches, ps.d_items + sub.first, sub.nitems, f, ws);
+          if (e != hipSuccess) break;
+        }
+      } else {
+        e = launch_line_pass(ps.line_kind, plan->cfg.precision, ps.ppt, ps.shape, s,
+                             plan->d_patches, ps.d_items, ps.nitems, f, ws);
+      }
       break;
     case kFused:
       e = launch_fused_z(plan->cfg.precision, plan->ndim, plan->src_form, ps.mpt, ps.shape,
-                         s, plan->d_patches, ps.d_items, ps.nitems, plan->ws, ph);
+                         s, plan->d_patches, ps.d_items, ps.nitems, ws, ph);
       break;
     case kUpdate:
       e = launch_update(plan->cfg.precision, plan->src_form, ps.shape, s, plan->d_patches,
-                        ps.d_items, ps.nitems, plan->ws, ph);
+                        ps.d_items, ps.nitems, ws, ph);
       break;
     case kWaveZ:
       e = wave2d::launch_z_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
-                                 ps.nitems, plan->ws, ph, ps.region);
+                                 ps.nitems, ws, ph, ps.region);
       break;
     case kFastXFwd:
-      e = fast2d::launch_x_fwd(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
+      e = fast2d::launch_x_fwd(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, ws);
       break;
     case kFastXInv:
-      e = fast2d::launch_x_inv(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, plan->ws);
+      e = fast2d::launch_x_inv(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, ws);
       break;
     default:
       e = fast2d::launch_z_fused(plan->cfg.source_mode, plan->cfg.order == 0, ps.shape, s,
-                                 plan->d_patches, ps.d_items, ps.nitems, plan->ws, ph);
+                                 plan->d_patches, ps.d_items, ps.nitems, ws, ph);
       break;
   }
   if (e != hipSuccess) return hip_fail(e, ps.name);
@@ -713,9 +863,9 @@ psatd_status check_fields(const psatd_plan_s* plan, const psatd_fields* f, Field
   return PSATD_OK;
 }
 
-psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStream_t s) {
+psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStream_t s, void* ws) {
   for (const Pass& ps : plan->passes) {
-    psatd_status st = enqueue_pass(plan, ps, fp, s);
+    psatd_status st = enqueue_pass(plan, ps, fp, s, ws);
     if (st != PSATD_OK) return st;
   }
   return PSATD_OK;
@@ -753,7 +903,7 @@ psatd_status build_graph(psatd_plan_s* plan) {
   fp.table = plan->d_fieldtab;
   e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  psatd_status cs = enqueue_step(plan, fp, plan->capture_stream);
+  psatd_status cs = enqueue_step(plan, fp, plan->capture_stream, plan->ws);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(plan->capture_stream, &graph);
   if (cs != PSATD_OK) {
@@ -826,10 +976,10 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
   constexpr int kReps = 3;
   // Mean ms of one launch of `ps` (warm-up first), or a negative value on error.
   auto time_pass = [&](const Pass& ps) -> double {
-    st = enqueue_pass(plan, ps, f, s);
+    st = enqueue_pass(plan, ps, f, s, plan->ws);
     if (st != PSATD_OK) return -1.0;
     e = hipEventRecord(e0, s);
-    for (int r = 0; r < kReps && st == PSATD_OK && e == hipSuccess; ++r) st = enqueue_pass(plan, ps, f, s);
+    for (int r = 0; r < kReps && st == PSATD_OK && e == hipSuccess; ++r) st = enqueue_pass(plan, ps, f, s, plan->ws);
     if (st != PSATD_OK) return -1.0;
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -856,6 +1006,22 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     std::vector<int> vars = {0};
     if (ps.type == kFused || ps.type == kWaveZ) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
     if (ps.type == kLine) vars = {4, kMaxPts};
+    if (ps.type == kLine && !ps.ct && ct_line_eligible(ps.line_kind, plan)) {
+      std::vector<WorkItem> its;
+      Pass c = make_ct_line_pass(ps.line_kind, plan, ps.comps, its);
+      WorkItem* d = nullptr;
+      if (verify_pass(plan, c, its.data()) == PSATD_OK) {
+        e = hipMalloc(&d, sizeof(WorkItem) * its.size());
+        if (e == hipSuccess)
+          e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+          c.d_items = d;
+          cands.push_back(Cand{c, d});
+        } else if (d) {
+          (void)hipFree(d);
+        }
+      }
+    }
     if (ps.type == kLine || ps.type == kFused || ps.type == kWaveZ) {
       for (int m : vars) {
         if (e != hipSuccess) break;
@@ -869,8 +1035,8 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
           }
           bool seen = false;
           for (const Cand& x : cands)
-            seen = seen || (x.pass.type == c.type && x.pass.lines == c.lines && x.pass.mpt == c.mpt &&
-                            x.pass.ppt == c.ppt);
+            seen = seen || (x.pass.type == c.type && x.pass.ct == c.ct && x.pass.lines == c.lines &&
+                            x.pass.mpt == c.mpt && x.pass.ppt == c.ppt);
           if (seen) continue;
           c.d_items = nullptr;
           if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
@@ -895,10 +1061,14 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
       // persistent grid of k workgroups per CU
       const int full = c.type == kWaveZ ? c.shape.grid : c.nitems;
       std::vector<int> grids = {full};
-      for (int k : {1, 2, 4, 8})
-        if (k * plan->num_cus < full) grids.push_back(k * plan->num_cus);
+      if (c.ct) {
+        grids = {0, 1, 2, 4, 8};  // per length launch: one workgroup per item, or k per CU
+      } else {
+        for (int k : {1, 2, 4, 8})
+          if (k * plan->num_cus < full) grids.push_back(k * plan->num_cus);
+      }
       for (int g : grids) {
-        c.shape.grid = g;
+        set_grid(plan, c, g);
         const double ms = time_pass(c);
         if (ms < 0.0) break;
         if (ms < best_ms) {
@@ -916,7 +1086,7 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
       ps = cands[best_c].pass;
       plan->extra_items.push_back(cands[best_c].d);
     }
-    ps.shape.grid = best_g;
+    set_grid(plan, ps, best_g);
     ps.tuned_ms = best_ms;
   }
   cleanup();
@@ -983,10 +1153,16 @@ psatd_status build_plan(psatd_plan_s* plan) {
   }
   const size_t fw_off = take(sizeof(double) * std::max<size_t>(1, fw.size()));
 
-  hipError_t e = hipMalloc(&plan->d_tables, tb);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
-  char* T = static_cast<char*>(plan->d_tables);
-  if (!fw.empty()) {
+  const bool dry = plan->dry;
+  hipError_t e = hipSuccess;
+  if (dry) {
+    plan->dry_tables.assign(tb, 0);
+  } else {
+    e = hipMalloc(&plan->d_tables, tb);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
+  }
+  char* T = dry ? plan->dry_tables.data() : static_cast<char*>(plan->d_tables);
+  if (!fw.empty() && !dry) {
     e = hipMemcpy(T + fw_off, fw.data(), sizeof(double) * fw.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(fornberg)");
   }
@@ -994,6 +1170,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
   const int nfw = static_cast<int>(fw.size());
 
   for (auto& kv : tw_off) {
+    if (dry) break;
     e = launch_twiddles(reinterpret_cast<double2*>(T + kv.second), kv.first, kv.first, nullptr);
     if (e != hipSuccess) return hip_fail(e, "twiddle table");
   }
@@ -1033,6 +1210,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
     fill(P.fy, P.ny, kMaxPts);
     fill(P.fz, P.nz, kMaxRadixZ);
     plan->host_patches.push_back(P);
+    if (dry) continue;
 
     e = launch_ktable(const_cast<double*>(P.kx), P.nx, d.d[0], P.mx, 1, d_fw, nfw, centered, nullptr);
     if (e == hipSuccess && plan->ndim == 3)
@@ -1064,11 +1242,13 @@ psatd_status build_plan(psatd_plan_s* plan) {
   if (plan->ndim == 3) spec_off *= 2;
   plan->ws_bytes = static_cast<size_t>(spec_off) * 2 * plan->elem;
 
-  e = hipMalloc(&plan->d_patches, sizeof(PatchDev) * plan->host_patches.size());
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(patches)");
-  e = hipMemcpy(plan->d_patches, plan->host_patches.data(),
-                sizeof(PatchDev) * plan->host_patches.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(patches)");
+  if (!dry) {
+    e = hipMalloc(&plan->d_patches, sizeof(PatchDev) * plan->host_patches.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(patches)");
+    e = hipMemcpy(plan->d_patches, plan->host_patches.data(),
+                  sizeof(PatchDev) * plan->host_patches.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(patches)");
+  }
 
   // ---- passes
   std::vector<int> in_comps, out_comps;
@@ -1081,49 +1261,59 @@ psatd_status build_plan(psatd_plan_s* plan) {
     plan->passes.push_back(make_fast_pass(kFastZ, plan, in_comps, items));
     plan->passes.push_back(make_fast_pass(kFastXInv, plan, out_comps, items));
   } else {
-    plan->passes.push_back(make_line_pass(kXFwd, plan, in_comps, items));
-  if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYFwd, plan, in_comps, items));
+    // compile-time line kernels where every length is compiled, else the
+    // generic ones (the autotuner times both)
+    auto line = [&](int kind, const std::vector<int>& comps) {
+      return ct_line_eligible(kind, plan) ? make_ct_line_pass(kind, plan, comps, items)
+                                          : make_line_pass(kind, plan, comps, items);
+    };
+    plan->passes.push_back(line(kXFwd, in_comps));
+  if (plan->ndim == 3) plan->passes.push_back(line(kYFwd, in_comps));
   if (cfg.path == PSATD_PATH_FUSED && wave_z_eligible(plan)) {
     plan->passes.push_back(make_wave_z_pass(plan, items));
-  } else if (cfg.path == PSATD_PATH_FUSED) {
+  } else if (cfg.path == PSATD_PATH_FUSED && fused_fits(plan, items)) {
     Pass fz;
     psatd_status st = make_fused_pass(plan, items, &fz);
     if (st != PSATD_OK) return st;
     plan->passes.push_back(fz);
   } else {
-    plan->passes.push_back(make_line_pass(kZFwd, plan, in_comps, items));
+    // the plain z passes: asked for, or the fused pass cannot hold a z line
+    plan->passes.push_back(line(kZFwd, in_comps));
     plan->passes.push_back(make_update_pass(plan, items));
-    plan->passes.push_back(make_line_pass(kZInv, plan, out_comps, items));
+    plan->passes.push_back(line(kZInv, out_comps));
   }
-  if (plan->ndim == 3) plan->passes.push_back(make_line_pass(kYInv, plan, out_comps, items));
-  plan->passes.push_back(make_line_pass(kXInv, plan, out_comps, items));
+  if (plan->ndim == 3) plan->passes.push_back(line(kYInv, out_comps));
+  plan->passes.push_back(line(kXInv, out_comps));
   }
 
   for (const Pass& ps : plan->passes) {
     psatd_status st = verify_pass(plan, ps, items.data() + reinterpret_cast<size_t>(ps.d_items));
     if (st != PSATD_OK) return st;
   }
-  e = hipMalloc(&plan->d_items, sizeof(WorkItem) * items.size());
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(work items)");
-  e = hipMemcpy(plan->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work items)");
-  for (Pass& ps : plan->passes)
-    ps.d_items = static_cast<WorkItem*>(plan->d_items) + reinterpret_cast<size_t>(ps.d_items);
+  if (!dry) {
+    e = hipMalloc(&plan->d_items, sizeof(WorkItem) * items.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(work items)");
+    e = hipMemcpy(plan->d_items, items.data(), sizeof(WorkItem) * items.size(),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work items)");
+    for (Pass& ps : plan->passes)
+      ps.d_items = static_cast<WorkItem*>(plan->d_items) + reinterpret_cast<size_t>(ps.d_items);
 
-  if (!(cfg.flags & PSATD_FLAG_NO_WORKSPACE)) {
-    e = hipMalloc(&plan->ws, plan->ws_bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
-    plan->ws_owned = true;
-  }
-  e = hipDeviceSynchronize();
-  if (e != hipSuccess) return hip_fail(e, "plan tables");
-  if (cfg.flags & PSATD_FLAG_AUTOTUNE) {
-    psatd_status st = autotune_passes(plan);
-    if (st != PSATD_OK) return st;
-  }
-  if (cfg.flags & PSATD_FLAG_GRAPH) {
-    psatd_status st = build_graph(plan);
-    if (st != PSATD_OK) return st;
+    if (!(cfg.flags & PSATD_FLAG_NO_WORKSPACE)) {
+      e = hipMalloc(&plan->ws, plan->ws_bytes);
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+      plan->ws_owned = true;
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "plan tables");
+    if (cfg.flags & PSATD_FLAG_AUTOTUNE) {
+      psatd_status st = autotune_passes(plan);
+      if (st != PSATD_OK) return st;
+    }
+    if (cfg.flags & PSATD_FLAG_GRAPH) {
+      psatd_status st = build_graph(plan);
+      if (st != PSATD_OK) return st;
+    }
   }
 
   char buf[512];
@@ -1136,9 +1326,11 @@ psatd_status build_plan(psatd_plan_s* plan) {
   plan->info += buf;
   for (const Pass& ps : plan->passes) {
     std::snprintf(buf, sizeof(buf),
-                  "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d ppt=%d lines=%d bytes=%.0f%s\n",
+                  "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d ppt=%d lines=%d bytes=%.0f kernel=%s%s\n",
                   ps.name, ps.nitems, ps.shape.grid, ps.shape.block, ps.shape.lds_bytes, ps.mpt,
-                  ps.ppt, ps.lines, ps.bytes, ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
+                  ps.ppt, ps.lines, ps.bytes,
+                  ps.type == kWaveZ ? "wave" : (ps.ct ? "compile-time" : (ps.type >= kFastXFwd ? "4096" : "generic")),
+                  ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
     plan->info += buf;
   }
   return PSATD_OK;
@@ -1201,6 +1393,27 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
   }
 }
 
+psatd_status psatd_plan_describe(const psatd_config* cfg, const psatd_patch_desc* patches,
+                                 int32_t npatches, size_t* ws_bytes, char* info, size_t len) {
+  try {
+    psatd_status st = validate(cfg, patches, npatches);
+    if (st != PSATD_OK) return st;
+    psatd_plan_s plan;
+    plan.cfg = *cfg;
+    plan.dry = true;
+    plan.desc.assign(patches, patches + npatches);
+    st = build_plan(&plan);
+    if (st != PSATD_OK) return st;
+    if (ws_bytes) *ws_bytes = plan.ws_bytes;
+    if (info && len > 0) std::snprintf(info, len, "%s", plan.info.c_str());
+    return PSATD_OK;
+  } catch (const std::exception& ex) {
+    return fail(PSATD_ERR_OOM, std::string("host allocation failed: ") + ex.what());
+  } catch (...) {
+    return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
 psatd_status psatd_workspace_size(psatd_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(PSATD_ERR_INVALID_ARG, "NULL argument");
   *bytes = plan->ws_bytes;
@@ -1247,7 +1460,7 @@ static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int
     for (int n = 0; n < nsteps && rs == PSATD_OK; ++n)
       for (int i = 0; i < np && rs == PSATD_OK; ++i) {
         (void)hipEventRecord(ev[2 * (n * np + i)], s);
-        rs = enqueue_pass(plan, plan->passes[i], fp, s);
+        rs = enqueue_pass(plan, plan->passes[i], fp, s, plan->ws);
         (void)hipEventRecord(ev[2 * (n * np + i) + 1], s);
       }
     hipError_t e = hipStreamSynchronize(s);
@@ -1285,7 +1498,7 @@ static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int
   }
 
   for (int n = 0; n < nsteps; ++n) {
-    st = enqueue_step(plan, fp, s);
+    st = enqueue_step(plan, fp, s, plan->ws);
     if (st != PSATD_OK) return st;
   }
   return PSATD_OK;

@@ -281,6 +281,378 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
   }
 }
 
+// ------------------------------------------------------------------ compile-time line passes
+// The same passes as line_pass_kernel for the line lengths the workloads use,
+// with the length, the tile (lines per workgroup), the block size and the
+// radix schedule fixed at compile time, so that every index of the loads,
+// the Stockham stages, the r2c/c2r pairs and the stores folds to shifts,
+// multiplications by constants and immediate offsets.  One kernel per pass
+// kind; each work item dispatches on its line length.  A tile never straddles
+// the A of the tile map (the planner checks it), so one division per tile
+// places its strided side.
+namespace ct {
+
+constexpr int kT = 512;  // threads per workgroup
+
+__host__ __device__ constexpr bool supported(int L) {
+  return L == 32 || L == 48 || L == 64 || L == 96 || L == 128 || L == 192 || L == 256 ||
+         L == 384 || L == 512 || L == 1024;
+}
+// points per thread per stage and lines per tile
+__host__ __device__ constexpr int ppt(int L) { return (L % 3 == 0) ? 6 : 8; }
+__host__ __device__ constexpr int tile_lines(int L) { return kT * ppt(L) / L; }
+
+// Radix schedule of radix_plan(L, 8): radix 8 while possible, then 4 or 2,
+// then the radix-3 stages.
+__host__ __device__ constexpr int nstages(int L) {
+  int a = 0, b = 0;
+  while (L % 2 == 0) { L /= 2; ++a; }
+  while (L % 3 == 0) { L /= 3; ++b; }
+  return a / 3 + (a % 3 != 0) + b;
+}
+__host__ __device__ constexpr int radix_at(int L, int i) {
+  int a = 0, b = 0;
+  while (L % 2 == 0) { L /= 2; ++a; }
+  while (L % 3 == 0) { L /= 3; ++b; }
+  const int n8 = a / 3;
+  if (i < n8) return 8;
+  if (a % 3 != 0) {
+    if (i == n8) return 1 << (a % 3);
+    return 3;
+  }
+  return 3;
+}
+__host__ __device__ constexpr int ns_at(int L, int i) {
+  int n = 1;
+  for (int j = 0; j < i; ++j) n *= radix_at(L, j);
+  return n;
+}
+
+template <int L, int I, int SIGN>
+__device__ __forceinline__ void stage(double2* lds, const double2* __restrict__ tw) {
+  constexpr int NL = tile_lines(L);
+  constexpr int R = radix_at(L, I);
+  constexpr int Ns = ns_at(L, I);
+  constexpr int nb = L / R;
+  constexpr int NB = NL * nb;
+  constexpr int BPT = (NB + kT - 1) / kT;
+  constexpr int step = L / (Ns * R);
+  static_assert(BPT * R <= 8, "points per thread");
+  // the thread index through an opaque copy: each stage computes its own
+  // addresses where it uses them, instead of every stage's addresses being
+  // computed up front and held in registers across the whole transform
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  double2 v[BPT][R];
+  double2 wt[BPT];
+  int ob[BPT];
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    const int b0 = tid + t * kT;
+    const int b = (NB % kT == 0 || b0 < NB) ? b0 : 0;  // idle slots read a valid butterfly
+    const int line = b / nb;
+    const int j = b - line * nb;
+    const int k = j % Ns;
+    if constexpr (Ns > 1) wt[t] = gload(tw, k * step);
+    const int src = line * L + j;
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[t][q] = lds[lpad(src + q * nb)];
+    ob[t] = (NB % kT == 0 || b0 < NB) ? line * L + (j - k) * R + k : -1;
+  }
+  if constexpr (Ns > 1) {
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+      double2 u = wt[t];
+      if constexpr (SIGN > 0) u.y = -u.y;
+      double2 uq = u;
+      v[t][1] = cmul(v[t][1], u);
+#pragma unroll
+      for (int q = 2; q < R; ++q) {
+        uq = cmul(uq, u);
+        v[t][q] = cmul(v[t][q], uq);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < BPT; ++t) {
+    DFT<R, SIGN>::run(v[t]);
+    if (ob[t] >= 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) lds[lpad(ob[t] + q * Ns)] = v[t][q];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int SIGN>
+__device__ __forceinline__ void fft(double2* lds, const double2* __restrict__ tw) {
+  static_for<0, nstages(L)>([&](auto ic) __attribute__((always_inline)) {
+    stage<L, decltype(ic)::value, SIGN>(lds, tw);
+  });
+}
+
+// op(row, k, W^k) for the pairs (k, L - k), k = 0..L/2, of the tile's lines
+template <int L, typename Op>
+__device__ __forceinline__ void for_pairs(const double2* __restrict__ post, Op&& op) {
+  constexpr int NL = tile_lines(L);
+  constexpr int NP = L / 2 + 1;
+  constexpr int total = NL * NP;
+  constexpr int rounds = (total + kT - 1) / kT;
+  constexpr int G = 4;  // pairs whose twiddles are requested together
+#pragma unroll
+  for (int r0 = 0; r0 < rounds; r0 += G) {
+    int row[G], kk[G];
+    double2 wk[G];
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int idx = tid + (r0 + g) * kT;
+      row[g] = -1;
+      if (r0 + g < rounds && idx < total) {
+        const int line = idx / NP;
+        kk[g] = idx - line * NP;
+        row[g] = line * L;
+        wk[g] = gload(post, kk[g]);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (row[g] >= 0) op(row[g], kk[g], wk[g]);
+  }
+  __syncthreads();
+}
+
+template <int L>
+__device__ __forceinline__ void r2c_post(double2* lds, const double2* __restrict__ post) {
+  for_pairs<L>(post, [&](int row, int k, double2 wk) __attribute__((always_inline)) {
+    if (k == 0) {
+      const double2 z = lds[lpad(row)];
+      lds[lpad(row)] = make_double2(z.x + z.y, z.x - z.y);
+      return;
+    }
+    const int km = L - k;
+    const double2 a = lds[lpad(row + k)];
+    const double2 b = lds[lpad(row + km)];
+    const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    const double2 d = make_double2(a.x - b.x, a.y + b.y);
+    const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);
+    const double2 wo = cmul(wk, o);
+    lds[lpad(row + k)] = cadd(e, wo);
+    if (km != k) lds[lpad(row + km)] = cconj(csub(e, wo));
+  });
+}
+
+template <int L>
+__device__ __forceinline__ void c2r_pre(double2* lds, const double2* __restrict__ post) {
+  for_pairs<L>(post, [&](int row, int k, double2 wk) __attribute__((always_inline)) {
+    if (k == 0) {
+      const double2 x = lds[lpad(row)];
+      lds[lpad(row)] = make_double2(x.x + x.y, x.x - x.y);
+      return;
+    }
+    const int km = L - k;
+    const double2 a = lds[lpad(row + k)];
+    const double2 b = lds[lpad(row + km)];
+    const double2 p = make_double2(a.x + b.x, a.y - b.y);
+    const double2 m = make_double2(a.x - b.x, a.y + b.y);
+    const double2 t1 = cmul(cconj(wk), m);
+    const double2 t2 = cmul(wk, cconj(m));
+    lds[lpad(row + k)] = make_double2(p.x - t1.y, p.y + t1.x);
+    if (km != k) lds[lpad(row + km)] = make_double2(p.x - t2.y, -p.y + t2.x);
+  });
+}
+
+template <typename S, int KIND, int L>
+__device__ __forceinline__ void tile(const PatchDev* P, const WorkItem& wi, const FieldPtrs& fields,
+                                     S* ws, double2* lds) {
+  using V = typename Vec2<S>::type;
+  constexpr int SIGN = (KIND == kXFwd || KIND == kYFwd || KIND == kZFwd) ? -1 : 1;
+  constexpr int NL = tile_lines(L);
+  constexpr int TOTAL = NL * L;
+  constexpr int PPT = (TOTAL + kT - 1) / kT;
+  const int tid = threadIdx.x;
+  const int nl = wi.count;
+  const int l0 = wi.first;
+  const FFTPlanDev* F = (KIND == kXFwd || KIND == kXInv)   ? &P->fx
+                        : (KIND == kYFwd || KIND == kYInv) ? &P->fy
+                                                           : &P->fz;
+  V* const blk_x = reinterpret_cast<V*>(ws) + P->off_spec + (long long)wi.comp * P->comp_stride;
+  V* const blk_z = reinterpret_cast<V*>(ws) + P->off_z + (long long)wi.comp * P->comp_stride;
+  V* spec = (KIND == kXFwd || KIND == kXInv || KIND == kYFwd) ? blk_x : blk_z;
+  V* spec_out = (KIND == kXFwd || KIND == kXInv || KIND == kYInv) ? blk_x : blk_z;
+  // strided side of the tile: element n of line r at tbase + r + n C
+  long long tbase = 0, C = 0;
+  if constexpr (KIND == kXFwd || KIND == kXInv || KIND == kYFwd || KIND == kYInv) {
+    const TileMap tm = tile_map(KIND, P);
+    tbase = tile_offset(tm, l0, 0);
+    C = tm.C;
+  }
+  // y passes: contiguous y line r of the tile starts at ybase + r ystep
+  long long ybase = 0, ystep = 0;
+  if constexpr (KIND == kYFwd || KIND == kYInv) {
+    ybase = yline_start(P, l0);
+    ystep = static_cast<long long>(P->mx) * P->ny;
+  }
+
+  // ---------------- load (all of a thread's elements in flight together)
+  V r[PPT];
+  if constexpr (KIND == kXInv || KIND == kYInv) {
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const int idx = tid + t * kT;  // line fastest: idx = n NL + line
+      const int line = idx % NL, n = idx / NL;
+      if ((TOTAL % kT == 0 || idx < TOTAL) && line < nl) r[t] = spec[tbase + line + n * C];
+    }
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const int idx = tid + t * kT;
+      const int line = idx % NL, n = idx / NL;
+      if ((TOTAL % kT == 0 || idx < TOTAL) && line < nl) lds[lpad(line * L + n)] = to_d2(r[t]);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const int idx = tid + t * kT;  // element fastest: idx = line L + n
+      const int line = idx / L, n = idx - line * L;
+      if ((TOTAL % kT == 0 || idx < TOTAL) && line < nl) {
+        if constexpr (KIND == kYFwd) {
+          r[t] = spec[ybase + line * ystep + n];
+        } else if constexpr (KIND == kXFwd) {
+          const V* src = reinterpret_cast<const V*>(static_cast<const S*>(field_ptr(fields, wi.comp)) +
+                                                    P->off_real);
+          r[t] = src[(long long)l0 * L + idx];
+        } else {
+          r[t] = spec[(long long)l0 * L + idx];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < PPT; ++t) {
+      const int idx = tid + t * kT;
+      if ((TOTAL % kT == 0 || idx < TOTAL) && idx / L < nl) lds[lpad(idx)] = to_d2(r[t]);
+    }
+  }
+  __syncthreads();
+
+  if constexpr (KIND == kXInv) c2r_pre<L>(lds, P->post);
+  fft<L, SIGN>(lds, F->tw);
+  if constexpr (KIND == kXFwd) r2c_post<L>(lds, P->post);
+
+  // ---------------- store
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const int idx = tid + t * kT;
+    if (!(TOTAL % kT == 0 || idx < TOTAL)) continue;
+    if constexpr (KIND == kXFwd || KIND == kYFwd) {
+      const int line = idx % NL, n = idx / NL;
+      if (line < nl) spec_out[tbase + line + n * C] = from_d2<V>(lds[lpad(line * L + n)]);
+    } else {
+      const int line = idx / L, n = idx - line * L;
+      if (line >= nl) continue;
+      const V val = from_d2<V>(lds[lpad(idx)]);
+      if constexpr (KIND == kXInv) {
+        V* dst = reinterpret_cast<V*>(static_cast<S*>(field_ptr(fields, wi.comp)) + P->off_real);
+        dst[(long long)l0 * L + idx] = val;
+      } else if constexpr (KIND == kYInv) {
+        spec_out[ybase + line * ystep + n] = val;
+      } else {
+        spec_out[(long long)l0 * L + idx] = val;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// One kernel per line length (a kernel holding every length behind a switch
+// would take the registers of the largest); a pass launches one per length.
+template <typename S, int KIND, int L>
+__global__ void __launch_bounds__(kT)
+ct_line_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items, int nitems,
+               FieldPtrs fields, S* __restrict__ ws) {
+  extern __shared__ double2 lds[];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem wi = items[xcd_local_order(it, nitems)];
+    tile<S, KIND, L>(patches + wi.patch, wi, fields, ws, lds);
+  }
+}
+
+}  // namespace ct
+
+bool ct_line_supported(int L) { return ct::supported(L); }
+int ct_line_tile(int L) { return ct::tile_lines(L); }
+
+template <typename S, int KIND>
+static hipError_t ct_launch_len(int L, const LaunchShape& sh, hipStream_t stream, const PatchDev* p,
+                                const WorkItem* it, int n, const FieldPtrs& f, S* ws) {
+#define PSATD_CT_CASE(LEN)                                                                     \
+  case LEN:                                                                                    \
+    hipLaunchKernelGGL((ct::ct_line_kernel<S, KIND, LEN>), dim3(sh.grid), dim3(ct::kT),        \
+                       sh.lds_bytes, stream, p, it, n, f, ws);                                 \
+    break;
+  switch (L) {
+    PSATD_CT_CASE(32) PSATD_CT_CASE(48) PSATD_CT_CASE(64) PSATD_CT_CASE(96) PSATD_CT_CASE(128)
+    PSATD_CT_CASE(192) PSATD_CT_CASE(256) PSATD_CT_CASE(384) PSATD_CT_CASE(512) PSATD_CT_CASE(1024)
+    default: return hipErrorInvalidValue;
+  }
+#undef PSATD_CT_CASE
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t ct_dispatch(int kind, int L, const LaunchShape& sh, hipStream_t stream,
+                              const PatchDev* p, const WorkItem* it, int n, const FieldPtrs& f,
+                              S* ws) {
+  switch (kind) {
+    case kXFwd: return ct_launch_len<S, kXFwd>(L, sh, stream, p, it, n, f, ws);
+    case kXInv: return ct_launch_len<S, kXInv>(L, sh, stream, p, it, n, f, ws);
+    case kYFwd: return ct_launch_len<S, kYFwd>(L, sh, stream, p, it, n, f, ws);
+    case kYInv: return ct_launch_len<S, kYInv>(L, sh, stream, p, it, n, f, ws);
+    case kZFwd: return ct_launch_len<S, kZFwd>(L, sh, stream, p, it, n, f, ws);
+    default: return ct_launch_len<S, kZInv>(L, sh, stream, p, it, n, f, ws);
+  }
+}
+
+hipError_t launch_ct_line(int kind, int precision, int L, const LaunchShape& sh, hipStream_t stream,
+                          const PatchDev* patches, const WorkItem* items, int nitems,
+                          const FieldPtrs& fields, void* ws) {
+  if (precision == 0)
+    return ct_dispatch<float>(kind, L, sh, stream, patches, items, nitems, fields, static_cast<float*>(ws));
+  return ct_dispatch<double>(kind, L, sh, stream, patches, items, nitems, fields, static_cast<double*>(ws));
+}
+
+template <typename S, int KIND>
+static void set_ct_attrs_kind(hipError_t& e) {
+  const int lim = 160 * 1024;
+  auto set = [&](const void* fn) {
+    hipError_t r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (r != hipSuccess) e = r;
+  };
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 32>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 48>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 64>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 96>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 128>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 192>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 256>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 384>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 512>));
+  set(reinterpret_cast<const void*>(&ct::ct_line_kernel<S, KIND, 1024>));
+}
+
+template <typename S>
+static hipError_t set_ct_attrs() {
+  hipError_t e = hipSuccess;
+  set_ct_attrs_kind<S, kXFwd>(e);
+  set_ct_attrs_kind<S, kXInv>(e);
+  set_ct_attrs_kind<S, kYFwd>(e);
+  set_ct_attrs_kind<S, kYInv>(e);
+  set_ct_attrs_kind<S, kZFwd>(e);
+  set_ct_attrs_kind<S, kZInv>(e);
+  return e;
+}
+
 // ------------------------------------------------------------------ fused z pass
 // (component groups: groups.hpp)
 template <typename S, int G, int SRC, int MPT>
@@ -763,6 +1135,8 @@ hipError_t configure_kernel_attributes() {
   if ((r = set_fused_attrs<double, 2, 2>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 2, 4>()) != hipSuccess) e = r;
   if ((r = set_fused_attrs<double, 3, 2>()) != hipSuccess) e = r;
+  if ((r = set_ct_attrs<float>()) != hipSuccess) e = r;
+  if ((r = set_ct_attrs<double>()) != hipSuccess) e = r;
   return e;
 }
 

@@ -40,6 +40,17 @@ hipError_t launch_line_pass(int kind, int precision, int ppt, const LaunchShape&
                             int nitems, const FieldPtrs& fields, void* ws);
 bool line_ppt_supported(int ppt);
 
+// Compile-time line passes: the line pass kinds above for the lengths
+// ct_line_supported() accepts, ct_line_tile(L) lines per work item (a work
+// item never crosses a multiple of the tile map's A), kCtBlock threads; one
+// launch covers the work items of one line length L.
+bool ct_line_supported(int L);
+int ct_line_tile(int L);
+hipError_t launch_ct_line(int kind, int precision, int L, const LaunchShape& sh, hipStream_t stream,
+                          const PatchDev* patches, const WorkItem* items, int nitems,
+                          const FieldPtrs& fields, void* ws);
+constexpr int kCtBlock = 512;
+
 // Fused z pass: forward FFT of the inputs along z, per-mode update, inverse
 // FFT of E', B' along z, all in one launch.  mpt = modes per thread.
 hipError_t launch_fused_z(int precision, int ndim, int src, int mpt, const LaunchShape& sh,

@@ -51,9 +51,14 @@ __device__ __forceinline__ void z_group(const PatchDev* P, const WorkItem& wi, f
   static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
     constexpr int slot = decltype(sc)::value;
     const float2* src = base + Gr::in[slot] * cs;
+    // an opaque copy of the lane offset: this component's loads are issued
+    // here, after the previous component's transform, not all at the start
+    // (each transform then holds its own registers only)
+    int lo = loff;
+    asm volatile("" : "+v"(lo));
     double2 v[NP];
 #pragma unroll
-    for (int m = 0; m < NP; ++m) v[m] = f2d(src[loff + S * m]);  // inactive lanes: a valid line
+    for (int m = 0; m < NP; ++m) v[m] = f2d(src[lo + S * m]);  // inactive lanes: a valid line
     wfft::fft<L, -1>(v, region, g, s, tw);
 #pragma unroll
     for (int m = 0; m < NP; ++m) held[slot][m] = d2f(v[m]);
@@ -64,7 +69,11 @@ __device__ __forceinline__ void z_group(const PatchDev* P, const WorkItem& wi, f
   const double dt = P->dt;
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    const double kz = gload(P->kz, s + S * m);
+    // one mode at a time: an opaque index keeps the next mode's work from
+    // being started (and held in registers) before this one is done
+    int iz = s + S * m;
+    asm volatile("" : "+v"(iz));
+    const double kz = gload(P->kz, iz);
     double2 E[3] = {}, B[3] = {}, J[3] = {};
     double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
     static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {

@@ -98,14 +98,19 @@ __device__ __forceinline__ void wave_sync() {
 // region (Line<L>::REGION elements); g, s: the lane's line and position;
 // tw[m] = exp(-2 pi i m / L) in FP64 (the plan's table for this length).
 template <int L, int SIGN>
-__device__ __forceinline__ void fft(double2 (&v)[Sched<L>::P], double2* region, int g, int s,
+__device__ __forceinline__ void fft(double2 (&v)[Sched<L>::P], double2* region, int g_in, int s_in,
                                     const double2* __restrict__ tw) {
   using LN = Line<L>;
   constexpr int P = LN::P;
   constexpr int S = LN::S;
-  double2* const line = region + g * LN::STRIDE;
   static_for<0, Sched<L>::N>([&](auto ic) __attribute__((always_inline)) {
     constexpr int I = decltype(ic)::value;
+    // the lane coordinates through opaque copies: each stage computes its own
+    // addresses and twiddle indices where it uses them, instead of all of them
+    // being computed once and held in registers across every transform
+    int s = s_in, g = g_in;
+    asm volatile("" : "+v"(s), "+v"(g));
+    double2* const line = region + g * LN::STRIDE;
     constexpr int R = Sched<L>::R[I];
     constexpr int Ns = ns_before<L>(I);
     constexpr int BPT = P / R;

@@ -207,3 +207,55 @@ def test_fdtd_validation_on_host(lib, scheme, desc, cfg, expect):
         assert lib.psatd_last_error().decode()
     assert lib.psatd_fdtd_push(None, None, 1, None) == -1
     assert lib.psatd_fdtd_destroy(None) == 0
+
+
+# ---- host-only planning (psatd_plan_describe): no GPU needed
+def _spec_elems(n, nin, ndim):
+    # k-space elements of one patch: nx/2 * ny * nz per input, padded to 64
+    m = n[0] // 2 * (n[1] if ndim == 3 else 1) * n[2]
+    return (m * nin + 63) // 64 * 64
+
+
+@pytest.mark.parametrize("shape,precision,source,nin", [
+    ((4096, 1, 4096), "fp32", "rho", 11),
+    ((512, 512, 512), "fp32", "vacuum", 6),
+    ((1024, 1024, 512), "fp32", "rho", 11),
+    ((256, 1, 384), "fp64", "j", 9),
+])
+def test_describe_workspace_matches_the_layout(lib, shape, precision, source, nin):
+    ndim = 3 if shape[1] > 1 else 2
+    p = pk.Patch(ndim, shape, (1.0, 1.0, 1.0), 0.3)
+    ws, info = pk.describe_plan([p], precision=precision, source_mode=source)
+    elem = 4 if precision == "fp32" else 8
+    blocks = 2 if ndim == 3 else 1  # 3D: a second block for the y passes
+    assert ws == _spec_elems(shape, nin, ndim) * blocks * 2 * elem
+    assert info.startswith(f"ndim={ndim} patches=1") and f"ws={ws}" in info
+
+
+def test_describe_batched_patches_workload(lib):
+    ps = [pk.Patch(2, (128, 1, 128), (1.0, 1.0, 1.0), 0.5) for _ in range(256)]
+    ws, info = pk.describe_plan(ps)
+    assert ws == 256 * _spec_elems((128, 1, 128), 6, 2) * 2 * 4
+    names = [ln.split()[0] for ln in info.splitlines()[1:]]
+    assert names[0].startswith("x") and names[-1].startswith("x") and len(names) == 3
+
+
+def test_describe_long_z_lines_fall_back_to_plain_z_passes(lib):
+    # FP64 2D holds at most 2048 modes per workgroup in the fused pass: the
+    # plan runs the plain z passes (transform, update, transform) instead
+    p = pk.Patch(2, (256, 1, 4096), (1.0, 1.0, 1.0), 0.5)
+    _, fused = pk.describe_plan([p], precision="fp64", path="fused")
+    _, plain = pk.describe_plan([p], precision="fp64", path="plain")
+    names = lambda s: [ln.split()[0] for ln in s.splitlines()[1:]]  # noqa: E731
+    assert names(fused) == names(plain) and "update" in names(fused)
+    _, short = pk.describe_plan([pk.Patch(2, (256, 1, 2048), (1.0, 1.0, 1.0), 0.5)], precision="fp64")
+    assert "update" not in names(short)
+
+
+def test_describe_reports_the_same_errors_as_plan(lib):
+    with pytest.raises(pk.PsatdError) as e:
+        pk.describe_plan([pk.Patch(2, (10, 1, 8), (1.0, 1.0, 1.0), 0.5)])
+    assert e.value.status == -2
+    with pytest.raises(pk.PsatdError) as e:
+        pk.describe_plan([pk.Patch(2, (64, 1, 64), (1.0, 1.0, 1.0), 0.9)], pstd=True)
+    assert e.value.status == -1 and "Courant" in str(e.value)
