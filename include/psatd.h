@@ -180,6 +180,26 @@ psatd_status psatd_set_workspace(psatd_plan_t plan, void* device_ptr, size_t byt
 psatd_status psatd_push(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
                         void* hip_stream);
 
+/* Bytes of the device-resident workspace of psatd_push_scratch. */
+#define PSATD_SCRATCH_BYTES (256u << 20)
+
+/* psatd_push for callers that cannot allocate device memory at all (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results as psatd_push, but the workspace
+ * is a fixed array of PSATD_SCRATCH_BYTES bytes that the library keeps in
+ * device memory, one copy per GPU, until the process ends.  The plan may be
+ * created with PSATD_FLAG_NO_WORKSPACE; its own workspace, graph and
+ * PSATD_FLAG_GRAPH are not used (the kernels are enqueued on hip_stream).
+ * Plans whose psatd_workspace_size exceeds PSATD_SCRATCH_BYTES are rejected
+ * with PSATD_ERR_WORKSPACE, nothing enqueued.  No allocation, host
+ * synchronization or host copy.  Every call on one GPU shares that GPU's
+ * array: calls that may overlap on one GPU (other streams, other threads,
+ * other plans) race and must be ordered by the caller.  Nothing in the array
+ * needs clearing: each step writes every workspace element it reads before
+ * reading it. */
+psatd_status psatd_push_scratch(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
+                                void* hip_stream);
+
 /* Like psatd_push, but records a HIP event pair around every kernel launch on
  * `hip_stream`, synchronizes at the end and writes the mean duration of each
  * pass in milliseconds to ms_per_pass[0 .. npass-1] (npass from

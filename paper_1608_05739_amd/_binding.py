@@ -38,9 +38,10 @@ EXPORTED_SYMBOLS = (
     "psatd_push_profiled", "psatd_pass_count", "psatd_pass_name", "psatd_pass_bytes",
     "psatd_plan_info", "psatd_destroy", "psatd_status_string", "psatd_last_error",
     "psatd_domain_create", "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
-    "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy",
+    "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy", "psatd_push_scratch",
     "psatd_plan_describe",
 )
+SCRATCH_BYTES = 256 << 20  # PSATD_SCRATCH_BYTES
 
 
 class PatchDesc(ctypes.Structure):
@@ -97,6 +98,7 @@ def load_library(path: Optional[str] = None):
     lib.psatd_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.psatd_set_workspace.argtypes = [vp, vp, sz]
     lib.psatd_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
+    lib.psatd_push_scratch.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
     lib.psatd_push_profiled.argtypes = [vp, ctypes.POINTER(Fields), i32, vp,
                                         ctypes.POINTER(ctypes.c_double), i32]
     lib.psatd_pass_count.argtypes = [vp, ctypes.POINTER(i32)]
@@ -120,7 +122,7 @@ def load_library(path: Optional[str] = None):
     lib.psatd_fdtd_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
     lib.psatd_fdtd_destroy.argtypes = [vp]
     for name in ("psatd_plan", "psatd_plan_describe", "psatd_workspace_size", "psatd_set_workspace", "psatd_push",
-                 "psatd_push_profiled", "psatd_pass_count", "psatd_pass_bytes",
+                 "psatd_push_scratch", "psatd_push_profiled", "psatd_pass_count", "psatd_pass_bytes",
                  "psatd_plan_info", "psatd_destroy", "psatd_domain_create",
                  "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
                  "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy"):
@@ -339,6 +341,13 @@ class Plan:
         f = self._fields(E, B, J, rho_old, rho_new)
         _check(self._lib, self._lib.psatd_push(self._plan, ctypes.byref(f), int(steps),
                                                 self._stream(stream)))
+
+    def push_scratch(self, E, B, J=None, rho_old=None, rho_new=None, steps=1, stream=None):
+        """Like :meth:`push`, on the library's device-resident workspace
+        (psatd_push_scratch: no allocation; workspace at most SCRATCH_BYTES)."""
+        f = self._fields(E, B, J, rho_old, rho_new)
+        _check(self._lib, self._lib.psatd_push_scratch(self._plan, ctypes.byref(f), int(steps),
+                                                        self._stream(stream)))
 
     def push_profiled(self, E, B, J=None, rho_old=None, rho_new=None, steps=1, stream=None):
         """Like :meth:`push`; returns the mean milliseconds of each pass (HIP events)."""

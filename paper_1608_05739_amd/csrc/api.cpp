@@ -22,7 +22,38 @@
 
 using namespace psatd;
 
+// Device-resident workspace of psatd_push_scratch: one copy per GPU the
+// library runs on, held until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: every host use goes
+// through the device address that hipGetSymbolAddress returned for the
+// current device (scratch_ptr below).
+static __device__ __align__(256) unsigned char scratch[PSATD_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` per device, looked up once per device at the
+// first plan created on it (with that device current).
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+psatd_status lookup_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return PSATD_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return PSATD_ERR_HIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return PSATD_OK;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 
 thread_local std::string g_last_error;
 
@@ -1364,6 +1395,8 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
         if (e == hipSuccess) e = fast2d::configure_attributes();
         if (e == hipSuccess) e = wave2d::configure_attributes();
         if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+        if (lookup_scratch(device) != PSATD_OK)
+          return fail(PSATD_ERR_HIP, "hipGetSymbolAddress(scratch) failed");
         configured.insert(device);
       }
     }
@@ -1508,6 +1541,37 @@ psatd_status psatd_push(psatd_plan_t plan, const psatd_fields* fields, int32_t n
                         void* hip_stream) {
   try {
     return push_impl(plan, fields, nsteps, hip_stream, nullptr, 0);
+  } catch (...) {
+    return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+psatd_status psatd_push_scratch(psatd_plan_t plan, const psatd_fields* fields, int32_t nsteps,
+                                void* hip_stream) {
+  try {
+    if (!plan) return fail(PSATD_ERR_INVALID_ARG, "plan is NULL");
+    if (nsteps < 0) return fail(PSATD_ERR_INVALID_ARG, "nsteps must be >= 0");
+    if (nsteps > 1 && plan->cfg.source_mode != PSATD_VACUUM)
+      return fail(PSATD_ERR_INVALID_ARG, "with sources, push one step at a time (nsteps = 1)");
+    if (plan->ws_bytes > static_cast<size_t>(PSATD_SCRATCH_BYTES))
+      return fail(PSATD_ERR_WORKSPACE,
+                  "the plan needs " + std::to_string(plan->ws_bytes) +
+                      " bytes of workspace; psatd_push_scratch holds at most " +
+                      std::to_string(static_cast<size_t>(PSATD_SCRATCH_BYTES)));
+    FieldPtrs fp;
+    psatd_status st = check_fields(plan, fields, &fp);
+    if (st != PSATD_OK) return st;
+    if (nsteps == 0) return PSATD_OK;
+    void* ws = scratch_ptr(plan->device);
+    if (!ws) return fail(PSATD_ERR_STATE, "no scratch address for the plan's device");
+    DeviceGuard g(plan->device);
+    if (!g.ok) return fail(PSATD_ERR_HIP, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    for (int n = 0; n < nsteps; ++n) {
+      st = enqueue_step(plan, fp, s, ws);
+      if (st != PSATD_OK) return st;
+    }
+    return PSATD_OK;
   } catch (...) {
     return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
   }
