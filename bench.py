@@ -488,8 +488,33 @@ def pass_report(plan, pass_ms):
     return passes, names[dom], pbytes[dom] / (pass_ms[dom] * 1e-3) / 1e9, sum(pbytes)
 
 
+def time_source_generator(w, steps):
+    """ms per step of the fixture's GPU source generator (J^{n+1/2} and
+    rho^{n+1} of one patch formed on the device, rho^n kept from the step
+    before), timed on its own: the timed field steps reuse one resident set
+    of sources, whose values do not change the cost of the step."""
+    import torch
+    from fixtures.device import DeviceSourceSchedule
+    gen = DeviceSourceSchedule(w.schedule[0], torch)
+    n = gen.cells
+    J = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty(n, dtype=torch.float32, device="cuda")
+    gen.advance_into(0, J, a, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        gen.advance_into(k, J, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    del gen, J, a, b
+    return {"kind": "fixture (torch elementwise kernels on the GPU, FP64 then rounded)",
+            "ms_per_step": ms, "steps": steps}
+
+
 def result_line(w_name, cells, steps, args, ms_step, value, cfg, dom_name, achieved, step_bytes,
-                passes, fp64, parity, cpu):
+                passes, fp64, parity, cpu, sources=None):
     traffic = measured_traffic(w_name, dom_name)
     return {
         "metric": METRIC,
@@ -513,6 +538,7 @@ def result_line(w_name, cells, steps, args, ms_step, value, cfg, dom_name, achie
         "fp64_plain": fp64,
         "parity": parity,
         "cpu_baseline": cpu,
+        "source_generator": sources,
     }
 
 
@@ -668,6 +694,11 @@ def main():
     plan.close()
     del E, B, J, ro, rn
 
+    sources = None
+    if w.sources and len(w.patches) == 1:
+        sources = time_source_generator(w, min(steps, 100))
+        log(f"[bench]   source generator (fixture, GPU): {sources['ms_per_step']:.4f} ms/step")
+
     # ------------------------------------------------ FP64 storage, plain path
     fp64, res64 = None, None
     if not args.skip_fp64:
@@ -690,7 +721,7 @@ def main():
            "arithmetic": "f64", "path": "fused", "graph": True, "autotune": True,
            "working_set_bytes": ws_bytes}
     out = result_line(w.name, cells, steps, args, ms_step, value, cfg, dom_name, achieved,
-                      step_bytes, passes, fp64, parity, cpu)
+                      step_bytes, passes, fp64, parity, cpu, sources)
     print(json.dumps(out), flush=True)
 
 

@@ -72,3 +72,61 @@ def workload4_device(torch, shape=None, device="cuda:0", dtype=None):
 
 
 NAME = CONFIG_NAMES[4]
+
+
+class DeviceSourceSchedule:
+    """The per-step sources of a :class:`fixtures.SourceSchedule`, generated on
+    the GPU.
+
+    The profiles P_c and their divergence factors D_c (FP64) are copied to the
+    device once; each step then forms
+        J_c = f_c(t^{n+1/2}) P_c,   rho^{n+1} = -dt sum_c F_c(n+1) D_c
+    with the host schedule's scalar coefficients, in the same FP64 operation
+    order as the host schedule, then rounds to the storage type.  rho^n of
+    step n is rho^{n+1} of step n - 1, kept from the previous call.
+    """
+
+    def __init__(self, schedule, torch, device="cuda:0", dtype=None):
+        self.torch = torch
+        self.s = schedule
+        self.dtype = dtype or torch.float32
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).to(device)  # noqa: E731
+        self.P = [dev(a) for a in schedule.P]
+        self.D = [dev(a) for a in schedule.D]
+        self.cells = self.P[0].numel()
+        self._tmp = torch.empty(self.cells, dtype=torch.float64, device=device)
+        self._acc = torch.empty(self.cells, dtype=torch.float64, device=device)
+
+    def _rho_into(self, F, out):
+        acc = self._acc
+        torch = self.torch
+        torch.mul(self.D[0], float(F[0]), out=acc)
+        for c in (1, 2):
+            torch.mul(self.D[c], float(F[c]), out=self._tmp)
+            acc.add_(self._tmp)
+        acc.mul_(-self.s.dt)
+        out[: self.cells].copy_(acc)
+
+    def sources_into(self, n, J, rho_old=None, rho_new=None):
+        """Write step n's J^{n+1/2} (3 flat tensors) and, if given, rho^n and
+        rho^{n+1} into the first ``cells`` elements of the given tensors."""
+        f, F0, F1 = self.s.coefficients(n)
+        for c in range(3):
+            self.torch.mul(self.P[c], float(f[c]), out=self._tmp)
+            J[c][: self.cells].copy_(self._tmp)
+        if rho_old is not None:
+            self._rho_into(F0, rho_old)
+        if rho_new is not None:
+            self._rho_into(F1, rho_new)
+
+    def advance_into(self, n, J, rho_old, rho_new):
+        """Step n's sources when the caller keeps rho_new of step n - 1 in
+        rho_old (the buffers swap roles each step): only J and rho^{n+1} are
+        formed.  Step 0 forms rho^0 too."""
+        f, F0, F1 = self.s.coefficients(n)
+        for c in range(3):
+            self.torch.mul(self.P[c], float(f[c]), out=self._tmp)
+            J[c][: self.cells].copy_(self._tmp)
+        if n == 0:
+            self._rho_into(F0, rho_old)
+        self._rho_into(F1, rho_new)

@@ -142,9 +142,10 @@ struct DeviceGuard {
 };
 
 enum PassType { kLine = 0, kFused = 1, kUpdate = 2, kFastXFwd = 3, kFastZ = 4, kFastXInv = 5,
-                kWaveZ = 6 };
+                kWaveZ = 6, kWaveX = 7 };
 
-// One launch of a compile-time line pass: the work items of one line length.
+// One launch of a pass compiled per length (compile-time line passes, the
+// wave-resident x passes): the work items of one line length.
 struct SubLaunch {
   int L = 0;
   int first = 0;  // index of its first work item within the pass's list
@@ -167,7 +168,7 @@ struct Pass {
   int lines = 0;           // line passes: lines per workgroup (the tile)
   int region = 0;          // wave-resident passes: double2 elements of LDS per wavefront
   bool ct = false;         // line passes: the compile-time-length kernels (ct_line_kernel),
-  std::vector<SubLaunch> subs;  // one launch per line length
+  std::vector<SubLaunch> subs;  // ct line and wave x passes: one launch per length
 };
 
 const char* line_pass_name(int kind) {
@@ -207,6 +208,11 @@ struct psatd_plan_s {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   FieldPtrs* d_fieldtab = nullptr;  // field pointers the graph's kernels read (FieldPtrs::table)
+  // graph capture: the launches of a pass with one launch per length run on
+  // side streams forked from the capture stream and joined back, so that the
+  // graph holds them as parallel branches (their tails overlap)
+  std::vector<hipStream_t> side_streams;
+  std::vector<hipEvent_t> fork_events;
   std::string info;
   // host-only planning (psatd_plan_describe): no device call is made, the
   // table addresses point into this host block and are never dereferenced
@@ -217,6 +223,10 @@ struct psatd_plan_s {
 namespace {
 
 void free_plan_memory(psatd_plan_s* p) {
+  for (hipEvent_t ev : p->fork_events) (void)hipEventDestroy(ev);
+  for (hipStream_t st : p->side_streams) (void)hipStreamDestroy(st);
+  p->fork_events.clear();
+  p->side_streams.clear();
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
@@ -366,10 +376,17 @@ int line_ppt(const psatd_plan_s* plan) {
   return (plan->cfg.flags & PSATD_FLAG_RADIX4_LINES) ? 4 : kMaxPts;
 }
 
-// Build a line pass over all patches for the given components.
+// Lines of a line pass between which a tile of the compile-time kernels may
+// not cross: the strided side of the x and y passes is placed by one division
+// per tile (the tile map's A), so a tile stays inside one run of A lines.
+int tile_period(int kind, const PatchDev& P) {
+  if (kind == kXFwd || kind == kXInv) return P.ndim == 2 ? P.nz : P.ny;
+  if (kind == kYFwd || kind == kYInv) return P.nz;
+  return 0;
+}
+
 // The compile-time line kernels take every patch of the plan if each line
-// length is compiled and no tile would straddle a multiple of the tile map's A
-// (the strided side of x and y passes; one division per tile places it).
+// length is compiled.
 bool ct_line_eligible(int kind, const psatd_plan_s* plan) {
   // (PSATD_FLAG_RADIX4_LINES asks for the generic radix-4 schedule)
   if (plan->cfg.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
@@ -377,11 +394,6 @@ bool ct_line_eligible(int kind, const psatd_plan_s* plan) {
     int nlines, L;
     line_geometry(kind, P, &nlines, &L);
     if (!ct_line_supported(L)) return false;
-    const int R = std::min(ct_line_tile(L), nlines);
-    int A = 0;
-    if (kind == kXFwd || kind == kXInv) A = P.ndim == 2 ? P.nz : P.ny;
-    if (kind == kYFwd || kind == kYInv) A = P.nz;
-    if (A > 0 && (R > A || A % R != 0)) return false;
   }
   return true;
 }
@@ -414,9 +426,14 @@ Pass make_ct_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int
       if (L != Lc) continue;
       const int R = std::min(ct_line_tile(L), nlines);
       ps.lines = std::max(ps.lines, R);
+      // tiles of R lines inside each run of A lines (the last one shorter
+      // where R does not divide A)
+      const int A = tile_period(kind, P) > 0 ? tile_period(kind, P) : nlines;
       for (int c : comps)
-        for (int l = 0; l < nlines; l += R)
-          items.push_back(WorkItem{static_cast<int>(pi), l, std::min(R, nlines - l), c});
+        for (int a0 = 0; a0 < nlines; a0 += A)
+          for (int l = a0; l < std::min(a0 + A, nlines); l += R)
+            items.push_back(
+                WorkItem{static_cast<int>(pi), l, std::min(R, std::min(a0 + A, nlines) - l), c});
       const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
       bytes += comps.size() * 2.0 * cells * plan->elem;
     }
@@ -434,17 +451,72 @@ Pass make_ct_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int
   return ps;
 }
 
-// Launch grid of a pass: g workgroups, or for the compile-time line passes
-// (one launch per length) g = 0 for one workgroup per item and g = k for at
-// most k workgroups per CU in each launch.
+// Wave-resident x passes (wavex.hip): 2D, FP32 storage, every row length
+// compiled.  (PSATD_FLAG_RADIX4_LINES asks for the generic radix-4 schedule.)
+bool wave_x_eligible(const psatd_plan_s* plan) {
+  const psatd_config& c = plan->cfg;
+  if (c.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
+  if (plan->ndim != 2 || c.precision != PSATD_FP32) return false;
+  for (const PatchDev& P : plan->host_patches)
+    if (!wave2d::x_supported(P.mx)) return false;
+  return true;
+}
+
+// Work items of x_rows_per_item(L) consecutive rows of one component, one
+// launch per row length.
+Pass make_wave_x_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
+                      std::vector<WorkItem>& items) {
+  Pass ps;
+  ps.type = kWaveX;
+  ps.line_kind = kind;
+  ps.name = line_pass_name(kind);
+  const size_t first = items.size();
+  double bytes = 0.0;
+  std::set<int> lengths;
+  for (const PatchDev& P : plan->host_patches) lengths.insert(P.mx);
+  size_t lds = 0;
+  for (int L : lengths) {
+    SubLaunch sub;
+    sub.L = L;
+    sub.first = static_cast<int>(items.size() - first);
+    const int T = wave2d::x_rows_per_item(L);
+    for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+      const PatchDev& P = plan->host_patches[pi];
+      if (P.mx != L) continue;
+      for (int c : comps)
+        for (int z = 0; z < P.nz; z += T)
+          items.push_back(WorkItem{static_cast<int>(pi), z, std::min(T, P.nz - z), c});
+      const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+      bytes += comps.size() * 2.0 * cells * plan->elem;
+    }
+    sub.nitems = static_cast<int>(items.size() - first) - sub.first;
+    const size_t sub_lds =
+        static_cast<size_t>(wave2d::z_region(L)) * wave2d::kWavesPerBlock * sizeof(double2);
+    sub.shape = LaunchShape{sub.nitems, wave2d::kBlock, sub_lds};
+    lds = std::max(lds, sub_lds);
+    ps.lines = std::max(ps.lines, T);
+    ps.subs.push_back(sub);
+  }
+  ps.nitems = static_cast<int>(items.size() - first);
+  ps.shape = LaunchShape{ps.nitems, wave2d::kBlock, lds};
+  ps.bytes = bytes;
+  ps.comps = comps;
+  ps.d_items = reinterpret_cast<WorkItem*>(first);
+  return ps;
+}
+
+// Launch grid of a pass: g workgroups, or for the passes launched per length
+// g = 0 for every item in a workgroup of its own and g = k for at most k
+// workgroups per CU in each launch.
 void set_grid(const psatd_plan_s* plan, Pass& ps, int g) {
-  if (!ps.ct) {
+  if (ps.subs.empty()) {
     ps.shape.grid = g;
     return;
   }
   int total = 0;
   for (SubLaunch& sub : ps.subs) {
-    sub.shape.grid = g == 0 ? sub.nitems : std::min(sub.nitems, g * plan->num_cus);
+    const int full = sub.nitems;
+    sub.shape.grid = g == 0 ? full : std::min(full, g * plan->num_cus);
     total += sub.shape.grid;
   }
   ps.shape.grid = total;
@@ -646,6 +718,25 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
         return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad block size");
       continue;
     }
+    if (ps.type == kWaveX) {
+      if (P.ndim != 2 || !wave2d::x_supported(P.mx))
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): row length not compiled");
+      if (w.comp < 0 || w.comp >= plan->nin)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): bad component");
+      if (w.count < 1 || w.first < 0 || w.first + w.count > P.nz ||
+          w.count > wave2d::x_rows_per_item(P.mx))
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): item out of range");
+      bool in_sub = false;
+      for (const SubLaunch& sub : ps.subs)
+        in_sub = in_sub ||
+                 (i >= sub.first && i < sub.first + sub.nitems && sub.L == P.mx &&
+                  sub.shape.block == wave2d::kBlock &&
+                  sub.shape.lds_bytes >= static_cast<size_t>(wave2d::z_region(P.mx)) *
+                                             wave2d::kWavesPerBlock * sizeof(double2));
+      if (!in_sub)
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): item outside its length's launch");
+      continue;
+    }
     if (ps.type == kWaveZ) {
       if (P.ndim != 2 || !wave2d::z_supported(P.nz))
         return fail(PSATD_ERR_STATE, "z_fused (wave): z length not compiled");
@@ -679,9 +770,7 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
         return fail(PSATD_ERR_STATE, std::string(ps.name) + ": bad component");
       if (w.count < 1 || w.first < 0 || w.first + w.count > nlines || w.count > ct_line_tile(L))
         return fail(PSATD_ERR_STATE, std::string(ps.name) + ": item out of range");
-      int A = 0;
-      if (ps.line_kind == kXFwd || ps.line_kind == kXInv) A = P.ndim == 2 ? P.nz : P.ny;
-      if (ps.line_kind == kYFwd || ps.line_kind == kYInv) A = P.nz;
+      const int A = tile_period(ps.line_kind, P);
       if (A > 0 && w.first / A != (w.first + w.count - 1) / A)
         return fail(PSATD_ERR_STATE, std::string(ps.name) + ": tile straddles the tile map");
       if (static_cast<size_t>(lpad_size(ct_line_tile(L) * L)) * sizeof(double2) > ps.shape.lds_bytes)
@@ -820,19 +909,47 @@ Pass make_wave_z_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
   return ps;
 }
 
+// Streams and events that let the launches of a per-length pass run as
+// parallel branches of a captured graph: ev[0] forks, ev[1 + i] joins launch i.
+struct Fork {
+  const hipStream_t* side = nullptr;
+  const hipEvent_t* ev = nullptr;
+};
+
+// Run launch(sub, stream) for every per-length launch of a pass: in order on
+// s, or (fork given, several launches) each on its own side stream that
+// waits for s and that s waits for.
+template <typename F>
+hipError_t for_subs(const Pass& ps, hipStream_t s, const Fork* fork, F&& launch) {
+  if (!fork || ps.subs.size() < 2) {
+    for (const SubLaunch& sub : ps.subs) {
+      const hipError_t e = launch(sub, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t e = hipEventRecord(fork->ev[0], s);
+  for (size_t i = 0; i < ps.subs.size() && e == hipSuccess; ++i) {
+    hipStream_t t = fork->side[i];
+    e = hipStreamWaitEvent(t, fork->ev[0], 0);
+    if (e == hipSuccess) e = launch(ps.subs[i], t);
+    if (e == hipSuccess) e = hipEventRecord(fork->ev[1 + i], t);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, fork->ev[1 + i], 0);
+  }
+  return e;
+}
+
 psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldPtrs& f,
-                          hipStream_t s, void* ws) {
+                          hipStream_t s, void* ws, const Fork* fork = nullptr) {
   hipError_t e;
   const Physics ph{plan->cfg.c, plan->cfg.eps0};
   switch (ps.type) {
     case kLine:
       if (ps.ct) {
-        e = hipSuccess;
-        for (const SubLaunch& sub : ps.subs) {
-          e = launch_ct_line(ps.line_kind, plan->cfg.precision, sub.L, sub.shape, s,
-                             plan->d_patches, ps.d_items + sub.first, sub.nitems, f, ws);
-          if (e != hipSuccess) break;
-        }
+        e = for_subs(ps, s, fork, [&](const SubLaunch& sub, hipStream_t t) {
+          return launch_ct_line(ps.line_kind, plan->cfg.precision, sub.L, sub.shape, t,
+                                plan->d_patches, ps.d_items + sub.first, sub.nitems, f, ws);
+        });
       } else {
         e = launch_line_pass(ps.line_kind, plan->cfg.precision, ps.ppt, ps.shape, s,
                              plan->d_patches, ps.d_items, ps.nitems, f, ws);
@@ -845,6 +962,12 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
     case kUpdate:
       e = launch_update(plan->cfg.precision, plan->src_form, ps.shape, s, plan->d_patches,
                         ps.d_items, ps.nitems, ws, ph);
+      break;
+    case kWaveX:
+      e = for_subs(ps, s, fork, [&](const SubLaunch& sub, hipStream_t t) {
+        return wave2d::launch_x(ps.line_kind, sub.L, sub.shape, t, plan->d_patches,
+                                ps.d_items + sub.first, sub.nitems, f, ws);
+      });
       break;
     case kWaveZ:
       e = wave2d::launch_z_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
@@ -894,9 +1017,11 @@ psatd_status check_fields(const psatd_plan_s* plan, const psatd_fields* f, Field
   return PSATD_OK;
 }
 
-psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStream_t s, void* ws) {
-  for (const Pass& ps : plan->passes) {
-    psatd_status st = enqueue_pass(plan, ps, fp, s, ws);
+psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStream_t s, void* ws,
+                          const std::vector<Fork>* forks = nullptr) {
+  for (size_t i = 0; i < plan->passes.size(); ++i) {
+    const Fork* fk = (forks && (*forks)[i].side) ? &(*forks)[i] : nullptr;
+    psatd_status st = enqueue_pass(plan, plan->passes[i], fp, s, ws, fk);
     if (st != PSATD_OK) return st;
   }
   return PSATD_OK;
@@ -930,11 +1055,37 @@ psatd_status build_graph(psatd_plan_s* plan) {
       return hip_fail(e, "capture stream");
     }
   }
+  // side streams and fork/join events for the per-length passes
+  size_t nside = 0, nev = 0;
+  for (const Pass& ps : plan->passes)
+    if (ps.subs.size() > 1) {
+      nside = std::max(nside, ps.subs.size());
+      nev += 1 + ps.subs.size();
+    }
+  while (plan->side_streams.size() < nside) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "side stream");
+    plan->side_streams.push_back(st);
+  }
+  while (plan->fork_events.size() < nev) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "fork event");
+    plan->fork_events.push_back(ev);
+  }
+  std::vector<Fork> forks(plan->passes.size());
+  for (size_t i = 0, k = 0; i < plan->passes.size(); ++i)
+    if (plan->passes[i].subs.size() > 1) {
+      forks[i].side = plan->side_streams.data();
+      forks[i].ev = plan->fork_events.data() + k;
+      k += 1 + plan->passes[i].subs.size();
+    }
   FieldPtrs fp{};
   fp.table = plan->d_fieldtab;
   e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  psatd_status cs = enqueue_step(plan, fp, plan->capture_stream, plan->ws);
+  psatd_status cs = enqueue_step(plan, fp, plan->capture_stream, plan->ws, &forks);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(plan->capture_stream, &graph);
   if (cs != PSATD_OK) {
@@ -1034,32 +1185,42 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     // per thread and radices up to 8 at 8; they round differently, and each
     // is checked against the oracle by the tests)
     // (the wave-resident z pass: also the generic fused pass, at every choice)
+    // (line passes: also the compile-time and the wave-resident kernels where
+    // they apply)
+    const bool linelike = ps.type == kLine || ps.type == kWaveX;
     std::vector<int> vars = {0};
     if (ps.type == kFused || ps.type == kWaveZ) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
-    if (ps.type == kLine) vars = {4, kMaxPts};
-    if (ps.type == kLine && !ps.ct && ct_line_eligible(ps.line_kind, plan)) {
-      std::vector<WorkItem> its;
-      Pass c = make_ct_line_pass(ps.line_kind, plan, ps.comps, its);
+    if (linelike) vars = {4, kMaxPts};
+    // a checked and uploaded candidate work list
+    auto add_cand = [&](Pass c, const std::vector<WorkItem>& its) {
+      if (verify_pass(plan, c, its.data()) != PSATD_OK) return;
       WorkItem* d = nullptr;
-      if (verify_pass(plan, c, its.data()) == PSATD_OK) {
-        e = hipMalloc(&d, sizeof(WorkItem) * its.size());
-        if (e == hipSuccess)
-          e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) {
-          c.d_items = d;
-          cands.push_back(Cand{c, d});
-        } else if (d) {
-          (void)hipFree(d);
-        }
+      e = hipMalloc(&d, sizeof(WorkItem) * its.size());
+      if (e == hipSuccess)
+        e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) {
+        c.d_items = d;
+        cands.push_back(Cand{c, d});
+      } else if (d) {
+        (void)hipFree(d);
       }
+    };
+    if (linelike && !(ps.type == kLine && ps.ct) && ct_line_eligible(ps.line_kind, plan)) {
+      std::vector<WorkItem> its;
+      add_cand(make_ct_line_pass(ps.line_kind, plan, ps.comps, its), its);
     }
-    if (ps.type == kLine || ps.type == kFused || ps.type == kWaveZ) {
+    if (linelike && ps.type != kWaveX && (ps.line_kind == kXFwd || ps.line_kind == kXInv) &&
+        wave_x_eligible(plan) && e == hipSuccess) {
+      std::vector<WorkItem> its;
+      add_cand(make_wave_x_pass(ps.line_kind, plan, ps.comps, its), its);
+    }
+    if (linelike || ps.type == kFused || ps.type == kWaveZ) {
       for (int m : vars) {
         if (e != hipSuccess) break;
         for (int R : {1, 2, 4, 8, 16, 32}) {
           std::vector<WorkItem> its;
           Pass c;
-          if (ps.type == kLine) {
+          if (linelike) {
             c = make_line_pass(ps.line_kind, plan, ps.comps, its, R, m);
           } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
             continue;
@@ -1092,8 +1253,8 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
       // persistent grid of k workgroups per CU
       const int full = c.type == kWaveZ ? c.shape.grid : c.nitems;
       std::vector<int> grids = {full};
-      if (c.ct) {
-        grids = {0, 1, 2, 4, 8};  // per length launch: one workgroup per item, or k per CU
+      if (!c.subs.empty()) {
+        grids = {0, 1, 2, 4, 8};  // per length launch: every item its own, or k per CU
       } else {
         for (int k : {1, 2, 4, 8})
           if (k * plan->num_cus < full) grids.push_back(k * plan->num_cus);
@@ -1295,6 +1456,8 @@ psatd_status build_plan(psatd_plan_s* plan) {
     // compile-time line kernels where every length is compiled, else the
     // generic ones (the autotuner times both)
     auto line = [&](int kind, const std::vector<int>& comps) {
+      if ((kind == kXFwd || kind == kXInv) && wave_x_eligible(plan))
+        return make_wave_x_pass(kind, plan, comps, items);
       return ct_line_eligible(kind, plan) ? make_ct_line_pass(kind, plan, comps, items)
                                           : make_line_pass(kind, plan, comps, items);
     };
@@ -1360,7 +1523,9 @@ psatd_status build_plan(psatd_plan_s* plan) {
                   "  %-10s items=%d grid=%d block=%d lds=%zu mpt=%d ppt=%d lines=%d bytes=%.0f kernel=%s%s\n",
                   ps.name, ps.nitems, ps.shape.grid, ps.shape.block, ps.shape.lds_bytes, ps.mpt,
                   ps.ppt, ps.lines, ps.bytes,
-                  ps.type == kWaveZ ? "wave" : (ps.ct ? "compile-time" : (ps.type >= kFastXFwd ? "4096" : "generic")),
+                  (ps.type == kWaveZ || ps.type == kWaveX)
+                      ? "wave"
+                      : (ps.ct ? "compile-time" : (ps.type >= kFastXFwd ? "4096" : "generic")),
                   ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
     plan->info += buf;
   }
@@ -1394,6 +1559,7 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
         hipError_t e = configure_kernel_attributes();
         if (e == hipSuccess) e = fast2d::configure_attributes();
         if (e == hipSuccess) e = wave2d::configure_attributes();
+        if (e == hipSuccess) e = wave2d::configure_x_attributes();
         if (e != hipSuccess) return hip_fail(e, "kernel attributes");
         if (lookup_scratch(device) != PSATD_OK)
           return fail(PSATD_ERR_HIP, "hipGetSymbolAddress(scratch) failed");

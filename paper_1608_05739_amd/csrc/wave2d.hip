@@ -44,7 +44,7 @@ __device__ __forceinline__ void z_group(const PatchDev* P, const WorkItem& wi, f
   float2* const base = reinterpret_cast<float2*>(ws) + P->off_z + static_cast<long long>(wi.first) * L;
   const int loff = (active ? g : 0) * L + s;
   const long long cs = P->comp_stride;
-  const double2* tw = P->fz.tw;
+  const wfft::TableTwiddles<L> tw{P->fz.tw};
 
   // forward transforms of the group's inputs, kept in FP32 until the update
   float2 held[NIN][NP];

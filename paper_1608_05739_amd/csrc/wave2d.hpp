@@ -28,5 +28,17 @@ hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
 
 hipError_t configure_attributes();
 
+// x passes over 2D patches (wavex.hip): a workgroup transforms a tile of
+// x_rows_per_item(L) consecutive rows of one component (L = nx / 2, the
+// complex row length).  kind: kXFwd (rows -> [kx][z] spectra) or kXInv.
+// One launch covers the items of patches with nx / 2 = L; the block holds
+// kWavesPerBlock regions of z_region(L) double2 elements of LDS.
+bool x_supported(int L);
+int x_rows_per_item(int L);
+hipError_t launch_x(int kind, int L, const LaunchShape& sh, hipStream_t stream,
+                    const PatchDev* patches, const WorkItem* items, int nitems,
+                    const FieldPtrs& fields, void* ws);
+hipError_t configure_x_attributes();
+
 }  // namespace wave2d
 }  // namespace psatd

@@ -92,14 +92,79 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ------------------------------------------------------------------ twiddles
+// Distinct twiddle bases a lane uses in stage I: butterfly t has
+// k_t = (s + S t) mod Ns, which is s mod Ns for every t when Ns <= S and
+// repeats with period Ns / S in t otherwise.
+template <int L>
+__host__ __device__ constexpr int nbases(int i) {
+  const int Ns = ns_before<L>(i);
+  const int bpt = Sched<L>::P / Sched<L>::R[i];
+  if (Ns == 1) return 0;
+  if (Ns <= Line<L>::S) return 1;
+  return (Ns / Line<L>::S) < bpt ? (Ns / Line<L>::S) : bpt;
+}
+
+// Where a transform takes its twiddle bases exp(-2 pi i k / (Ns R)) from.
+//
+// Twiddles<L>: the lane's bases of every stage, loaded once and kept in
+// registers.  They depend only on the lane's position s, so every transform
+// of the length (forward, and conjugated for the inverse) uses the same ones.
+// For kernels that run one transform per tile.
+template <int L>
+struct Twiddles {
+  double2 w[4][4];
+
+  template <int I>
+  __device__ __forceinline__ double2 base(int t, int /*s*/) const {
+    // a copy the optimizer cannot see through: the powers of the base are
+    // formed in each transform, not kept live from one transform to the next
+    double2 u = w[I][t];
+    asm volatile("" : "+v"(u.x), "+v"(u.y));
+    return u;
+  }
+
+  // tw[m] = exp(-2 pi i m / L) in FP64 (the plan's table for this length)
+  __device__ __forceinline__ void load(const double2* __restrict__ tw, int s) {
+    static_for<0, Sched<L>::N>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int Ns = ns_before<L>(I);
+      constexpr int step = L / (Ns * Sched<L>::R[I]);
+#pragma unroll
+      for (int t = 0; t < nbases<L>(I); ++t) {
+        const int k = (Ns <= Line<L>::S) ? (s % Ns) : (s + Line<L>::S * t);
+        w[I][t] = gload(tw, k * step);
+      }
+    });
+  }
+};
+
+// TableTwiddles<L>: each transform loads its bases from the plan's table
+// again, through an index the optimizer cannot see through, instead of
+// keeping them (and their powers) live from one transform to the next.  For
+// kernels that hold other state across many transforms.
+template <int L>
+struct TableTwiddles {
+  const double2* tw;  // tw[m] = exp(-2 pi i m / L), FP64
+
+  template <int I>
+  __device__ __forceinline__ double2 base(int t, int s) const {
+    constexpr int Ns = ns_before<L>(I);
+    constexpr int step = L / (Ns * Sched<L>::R[I]);
+    int k = (Ns <= Line<L>::S) ? (s % Ns) : (s + Line<L>::S * t);
+    asm volatile("" : "+v"(k));
+    return gload(tw, k * step);
+  }
+};
+
 // ------------------------------------------------------------------ the transform
 // In-place FFT (unnormalized) of the G lines a wave holds.  v[m] = point
 // s + S m of the lane's line on entry and on exit.  region: this wave's LDS
 // region (Line<L>::REGION elements); g, s: the lane's line and position;
-// tw[m] = exp(-2 pi i m / L) in FP64 (the plan's table for this length).
-template <int L, int SIGN>
+// tws: the lane's twiddle bases (Twiddles<L> or TableTwiddles<L>).
+template <int L, int SIGN, typename TW>
 __device__ __forceinline__ void fft(double2 (&v)[Sched<L>::P], double2* region, int g_in, int s_in,
-                                    const double2* __restrict__ tw) {
+                                    const TW& tws) {
   using LN = Line<L>;
   constexpr int P = LN::P;
   constexpr int S = LN::S;
@@ -118,18 +183,12 @@ __device__ __forceinline__ void fft(double2 (&v)[Sched<L>::P], double2* region, 
     // twiddle bases w_t = exp(SIGN 2 pi i k_t / (Ns R)), k_t = (s + S t) mod Ns
     double2 wb[BPT];
     if constexpr (Ns > 1) {
-      constexpr int step = L / (Ns * R);
 #pragma unroll
       for (int t = 0; t < BPT; ++t) {
-        int k = (Ns <= S) ? (s % Ns) : (s + S * (t % (Ns / S)));
-        if (Ns <= S && t > 0) {
-          wb[t] = wb[0];
+        if (t >= nbases<L>(I)) {
+          wb[t] = wb[t % nbases<L>(I)];
         } else {
-          // an index the optimizer cannot see through: each transform loads
-          // its twiddles again instead of keeping them (and their powers)
-          // live from one transform to the next
-          asm volatile("" : "+v"(k));
-          double2 w = gload(tw, k * step);
+          double2 w = tws.template base<I>(t, s);
           if constexpr (SIGN > 0) w.y = -w.y;
           wb[t] = w;
         }

@@ -138,6 +138,79 @@ def test_fused_modes_per_thread_fallbacks(index, shape, mpt):
     assert err < TOL["fp32"]
 
 
+# ----------------------------------------------------------------- fused plans, long z lines
+# z lines longer than a workgroup of the fused pass holds: the fused plan runs
+# the plain z passes (transform, update, transform) for them instead.
+@pytest.mark.parametrize("index,shape,precision", [
+    (1, (4096, 4), "fp64"), (1, (3072, 6), "fp64"), (2, (4096, 2, 4), "fp32"),
+    (2, (2048, 2, 2), "fp64")])
+def test_fused_plan_with_too_long_z_lines_runs_plain_z_passes(index, shape, precision):
+    import paper_1608_05739_amd as pk
+    w = _w(index, shape, 3)
+    plan = pk.Plan(w.patches, precision=precision, source_mode="rho", path="fused")
+    info = plan.info
+    plan.close()
+    assert "update" in info and "z_fused" not in info, info
+    say(f"fused {precision} {shape}: plain z passes")
+    err = compare(run_gpu(w, precision, "fused", w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
+    assert err < TOL[precision]
+
+
+# the radix-4 option keeps the default schedule for lines over 2048 points
+@pytest.mark.parametrize("shape,precision,path", [((4096, 4), "fp32", "plain"),
+                                                  ((4, 4096), "fp64", "plain"),
+                                                  ((4096, 8), "fp32", "fused")])
+def test_radix4_option_with_4096_point_lines(shape, precision, path):
+    w = _w(1, shape, 3)
+    say(f"radix-4 option {shape} {precision} {path}")
+    err = compare(run_gpu(w, precision, path, w.steps, radix4_lines=True),
+                  run_oracle(w, precision, w.steps), precision=precision)
+    assert err < TOL[precision]
+
+
+# ----------------------------------------------------------------- compile-time line tiles
+# Tiles of the compile-time line kernels stay inside one run of the tile map
+# (z in 2D x passes, y in 3D x passes, z in y passes): where the tile does not
+# divide that run, its last tile is shorter.
+@pytest.mark.parametrize("index,shape", [(1, (96, 128)), (1, (48, 96)), (2, (48, 96, 64)),
+                                         (2, (18, 12, 64)), (2, (24, 32, 96))])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_compile_time_line_tiles_split_at_the_tile_map(index, shape, precision):
+    import paper_1608_05739_amd as pk
+    w = _w(index, shape, 3)
+    plan = pk.Plan(w.patches, precision=precision, source_mode="rho", path="fused")
+    info = plan.info
+    plan.close()
+    # (2D FP32 plans take the wave-resident x passes; their y and z passes
+    # do not exist or are fused, so only 3D or FP64 plans show the kernels)
+    want = "kernel=wave" if (index == 1 and precision == "fp32") else "kernel=compile-time"
+    assert want in info, info
+    say(f"compile-time tiles {shape} {precision}")
+    err = compare(run_gpu(w, precision, "fused", w.steps), run_oracle(w, precision, w.steps),
+                  precision=precision)
+    assert err < TOL[precision]
+
+
+# ----------------------------------------------------------------- wave-resident x passes
+# 2D FP32 plans run the x passes as wave-resident transforms over tiles of
+# consecutive rows; every compiled row length nx / 2, row counts that leave a
+# partial last tile, both paths, with sources.
+@pytest.mark.parametrize("shape", [(36, 64), (18, 96), (24, 128), (12, 192), (54, 256),
+                                   (6, 384), (72, 512), (6, 768), (18, 1024)])
+@pytest.mark.parametrize("path", ["fused", "plain"])
+def test_wave_x_passes_every_row_length(shape, path):
+    import paper_1608_05739_amd as pk
+    w = _w(1, shape, 3)
+    plan = pk.Plan(w.patches, precision="fp32", source_mode="rho", path=path)
+    info = plan.info
+    plan.close()
+    assert info.count("kernel=wave") >= 2, info
+    say(f"wave x passes {shape} fp32 {path}")
+    err = compare(run_gpu(w, "fp32", path, w.steps), run_oracle(w, "fp32", w.steps))
+    assert err < TOL["fp32"]
+
+
 # ----------------------------------------------------------------- batched patches
 def test_batched_patches_workload3_subset():
     w = fixtures.workload(3, npatches=24, steps=3)
@@ -164,6 +237,22 @@ def test_graph_replay_equals_eager():
     w = fixtures.workload(0, steps=10)
     a = run_gpu(w, "fp32", "fused", 10, graph=False)
     b = run_gpu(w, "fp32", "fused", 10, graph=True)
+    for pa, pb in zip(a[0] + a[1], b[0] + b[1]):
+        for x, y in zip(pa, pb):
+            assert np.array_equal(x, y)
+
+
+def test_graph_with_parallel_length_launches_equals_eager():
+    # a batch of patches of several sizes: the graph runs the per-length
+    # launches of each pass as parallel branches
+    import paper_1608_05739_amd as pk
+    w = fixtures.workload(3, npatches=24, steps=6)
+    plan = pk.Plan(w.patches, precision="fp32", source_mode="vacuum", path="fused")
+    info = plan.info
+    plan.close()
+    assert "kernel=wave" in info, info
+    a = run_gpu(w, "fp32", "fused", 6, graph=False)
+    b = run_gpu(w, "fp32", "fused", 6, graph=True)
     for pa, pb in zip(a[0] + a[1], b[0] + b[1]):
         for x, y in zip(pa, pb):
             assert np.array_equal(x, y)
