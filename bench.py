@@ -70,22 +70,46 @@ def measured_traffic(workload, kernel):
     return ent.get("bytes_per_launch")
 
 
-# rocprofv3 kernel names -> pass names (the 4096 x 4096 kernels and the
-# generic ones: line_pass_kernel<S, KIND, PPT>, KIND 0 x fwd, 1 x inv, 2 y fwd,
-# 3 y inv; the wave-resident 2D kernels carry the pass in their name)
+# rocprofv3 kernel names -> pass names: the 4096 x 4096 kernels, the wave
+# z pass, and the line kernels whose template argument KIND names the pass
+# (line_pass_kernel<S, KIND, PPT>, ct_line_kernel<S, KIND, L>,
+# wave_x_kernel<KIND, L>; KIND 0 x fwd, 1 x inv, 2 y fwd, 3 y inv, 4 z fwd,
+# 5 z inv)
+LINE_KINDS = {"0": "x_r2c_fwd", "1": "x_c2r_inv", "2": "y_c2c_fwd", "3": "y_c2c_inv",
+              "4": "z_c2c_fwd", "5": "z_c2c_inv"}
+
+
 def pass_of_kernel(name):
     import re
     for key, pname in (("x_fwd_kernel", "x_r2c_fwd"), ("z_fused_kernel", "z_fused"),
                        ("x_inv_kernel", "x_c2r_inv"), ("fused_z_kernel", "z_fused"),
-                       ("wave_z_fused", "z_fused"), ("wave_x_fwd", "x_r2c_fwd"),
-                       ("wave_x_inv", "x_c2r_inv")):
+                       ("wave_z_fused", "z_fused"), ("update_kernel", "update")):
         if key in name:
             return pname
-    m = re.search(r"line_pass_kernel<[^,]+, ?(\d)", name)
+    m = (re.search(r"(?:line_pass_kernel|ct_line_kernel)<[^,<>]+, ?(\d)", name)
+         or re.search(r"wave_x_kernel<(\d)", name))
     if m:
-        return {"0": "x_r2c_fwd", "1": "x_c2r_inv", "2": "y_c2c_fwd", "3": "y_c2c_inv",
-                "4": "z_c2c_fwd", "5": "z_c2c_inv"}[m.group(1)]
+        return LINE_KINDS[m.group(1)]
     return None
+
+
+def final_dispatches(rows):
+    """The plan's final launches in a list of (kernel, grid, ...) dispatches in
+    dispatch order (pass kernels only): the set of (kernel, grid) of the last
+    step -- walking back from the end until one repeats -- and the trailing
+    run of dispatches drawn from that set (the timed and profiled steps; the
+    autotuner's trial launches at plan time come before it)."""
+    last = set()
+    for r in reversed(rows):
+        if (r[0], r[1]) in last:
+            break
+        last.add((r[0], r[1]))
+    out = []
+    for r in reversed(rows):
+        if (r[0], r[1]) not in last:
+            break
+        out.append(r)
+    return out[::-1]
 
 
 def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
@@ -101,10 +125,15 @@ def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] == counter:
-                    out.append((r["Kernel_Name"], float(r["Counter_Value"])))
-        return out
+                    grid = r.get("Grid_Size") or r.get("Grid_Size_X") or "0"
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(grid),
+                                float(r["Counter_Value"])))
+        out.sort()
+        return [(n, g, v) for _, n, g, v in out]
 
-    fetch, write = rows(fetch_csv, "FETCH_SIZE"), rows(write_csv, "WRITE_SIZE")
+    fetch_all, write_all = rows(fetch_csv, "FETCH_SIZE"), rows(write_csv, "WRITE_SIZE")
+    fetch = [(n, v) for n, _, v in fetch_all]
+    write = [(n, v) for n, _, v in write_all]
     kib = calib_mib * 1024.0
     # the calibration copy: the first copy kernel whose WRITE_SIZE is the copied size
     wcal = next(v for n, v in write if "copy" in n.lower() and abs(v - kib) < 0.01 * kib)
@@ -117,17 +146,28 @@ def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
     except (OSError, ValueError):
         data = {}
     h = kernel_source_hash()
+    # the plan's final kernels only (not the autotuner's trial launches)
+    fetch = [(n, v) for n, _, v in final_dispatches([r for r in fetch_all if pass_of_kernel(r[0])])]
+    write = [(n, v) for n, _, v in final_dispatches([r for r in write_all if pass_of_kernel(r[0])])]
     passes = sorted({pass_of_kernel(n) for n, _ in fetch} - {None})
     for pname in passes:
-        fv = [v for n, v in fetch if pass_of_kernel(n) == pname]
-        wv = [v for n, v in write if pass_of_kernel(n) == pname]
-        if not fv or not wv:
+        # a pass launched per length: one kernel per length, each once a step
+        f_kib = w_kib = 0.0
+        ndisp = 0
+        for kname in sorted({n for n, _ in fetch if pass_of_kernel(n) == pname}):
+            fv = [v for n, v in fetch if n == kname]
+            wv = [v for n, v in write if n == kname]
+            if not fv or not wv:
+                continue
+            f_kib += sum(fv) / len(fv)
+            w_kib += sum(wv) / len(wv)
+            ndisp += len(fv)
+        if ndisp == 0:
             continue
-        f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
         data[f"{name}:{pname}"] = {
             "bytes_per_launch": (f_kib * fscale + w_kib * wscale) * 1024.0,
             "fetch_kib": f_kib, "write_kib": w_kib, "fetch_scale": fscale, "write_scale": wscale,
-            "dispatches": len(fv), "source_hash": h}
+            "dispatches": ndisp, "source_hash": h}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)

@@ -26,105 +26,138 @@ __device__ __forceinline__ float2 d2f(double2 v) {
   return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
 }
 
-template <int L, int SRC, int GR>
-__device__ __forceinline__ void z_group(const PatchDev* P, const WorkItem& wi, float* ws,
-                                        const Physics& ph, double2* region, int lane) {
+// Per-item state of a wave: its lines, the lane's position, and the values
+// it requests once per item (twiddle bases, mode wavenumbers, kx).
+template <int L>
+struct ZItem {
   using LN = wfft::Line<L>;
-  using Gr = Group<GR, SRC>;
-  constexpr int NP = LN::P;
-  constexpr int S = LN::S;
-  constexpr int NIN = Gr::nin;
-  const int g = lane / S;
-  const int s = lane % S;
-  const bool active = g < wi.count;
-  const int line = wi.first + (active ? g : 0);
+  static constexpr int NP = LN::P;
+  static constexpr int S = LN::S;
+  const PatchDev* P;
+  int g, s;
+  bool active;
   // wave-uniform base of the item's first line (scalar registers) and the
   // lane's 32-bit element offset, so that loads and stores address as
   // scalar base + lane offset + immediate
-  float2* const base = reinterpret_cast<float2*>(ws) + P->off_z + static_cast<long long>(wi.first) * L;
-  const int loff = (active ? g : 0) * L + s;
-  const long long cs = P->comp_stride;
-  const wfft::TableTwiddles<L> tw{P->fz.tw};
+  float2* base;
+  int loff;
+  long long cs;
+  wfft::Twiddles<L> tw;
+  double kzv[NP];
+  double kx;
 
-  // forward transforms of the group's inputs, kept in FP32 until the update
+  __device__ __forceinline__ ZItem(const PatchDev* p, const WorkItem& wi, float* ws, int lane)
+      : P(p), g(lane / S), s(lane % S) {
+    active = g < wi.count;
+    base = reinterpret_cast<float2*>(ws) + P->off_z + static_cast<long long>(wi.first) * L;
+    loff = (active ? g : 0) * L + s;  // inactive lanes: a valid line
+    cs = P->comp_stride;
+    tw.load(P->fz.tw, s);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) kzv[m] = gload(P->kz, s + S * m);
+    kx = gload(P->kx, wi.first + (active ? g : 0));
+  }
+};
+
+// One polarization set: its inputs' loads (all requested at once), their
+// forward transforms and the per-mode update, and the inverse transforms of
+// the outputs with their stores.  The phases are separate so that the next
+// set's loads can be issued while this set's inverse transforms run.
+template <int L, int SRC, int GR>
+struct ZSet {
+  using Gr = Group<GR, SRC>;
+  static constexpr int NP = wfft::Line<L>::P;
+  static constexpr int NIN = Gr::nin;
   float2 held[NIN][NP];
-  static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
-    constexpr int slot = decltype(sc)::value;
-    const float2* src = base + Gr::in[slot] * cs;
-    // an opaque copy of the lane offset: this component's loads are issued
-    // here, after the previous component's transform, not all at the start
-    // (each transform then holds its own registers only)
-    int lo = loff;
-    asm volatile("" : "+v"(lo));
-    double2 v[NP];
-#pragma unroll
-    for (int m = 0; m < NP; ++m) v[m] = f2d(src[lo + S * m]);  // inactive lanes: a valid line
-    wfft::fft<L, -1>(v, region, g, s, tw);
-#pragma unroll
-    for (int m = 0; m < NP; ++m) held[slot][m] = d2f(v[m]);
-  });
 
-  // per-mode update (kx of the line, kz of mode s + S m)
-  const double kx = gload(P->kx, line);
-  const double dt = P->dt;
-#pragma unroll
-  for (int m = 0; m < NP; ++m) {
-    // one mode at a time: an opaque index keeps the next mode's work from
-    // being started (and held in registers) before this one is done
-    int iz = s + S * m;
-    asm volatile("" : "+v"(iz));
-    const double kz = gload(P->kz, iz);
-    double2 E[3] = {}, B[3] = {}, J[3] = {};
-    double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+  __device__ __forceinline__ void load(const ZItem<L>& it) {
     static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
       constexpr int slot = decltype(sc)::value;
-      constexpr int comp = Gr::in[slot];
-      const double2 v = f2d(held[slot][m]);
-      if constexpr (comp < 3) E[comp] = v;
-      else if constexpr (comp < 6) B[comp - 3] = v;
-      else if constexpr (comp < 9) J[comp - 6] = v;
-      else if constexpr (comp == kRhoOld) ro = v;
-      else rn = v;
+      const float2* src = it.base + Gr::in[slot] * it.cs;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) held[slot][m] = src[it.loff + ZItem<L>::S * m];
     });
-    double2 Eo[3], Bo[3];
-    if constexpr (src_is_pstd(SRC)) {
-      pstd_update_mode<SRC>(kx, 0.0, kz, dt, ph.c, ph.eps0, P->inv_n, E, B, J, Eo, Bo);
-    } else {
-      const double K = sqrt(kx * kx + kz * kz);
-      const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, P->inv_n);
-      update_mode<SRC>(kx, 0.0, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+  }
+
+  // forward transforms one at a time (kept in FP32 until the update), then
+  // the update of every mode (kx of the line, kz of mode s + S m)
+  __device__ __forceinline__ void forward_update(const ZItem<L>& it, const Physics& ph,
+                                                 double2* region) {
+    static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+      constexpr int slot = decltype(sc)::value;
+      double2 v[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) v[m] = f2d(held[slot][m]);
+      wfft::fft<L, -1>(v, region, it.g, it.s, it.tw);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) held[slot][m] = d2f(v[m]);
+    });
+    const double dt = it.P->dt;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const double kz = it.kzv[m];
+      double2 E[3] = {}, B[3] = {}, J[3] = {};
+      double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
+      static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
+        constexpr int slot = decltype(sc)::value;
+        constexpr int comp = Gr::in[slot];
+        const double2 v = f2d(held[slot][m]);
+        if constexpr (comp < 3) E[comp] = v;
+        else if constexpr (comp < 6) B[comp - 3] = v;
+        else if constexpr (comp < 9) J[comp - 6] = v;
+        else if constexpr (comp == kRhoOld) ro = v;
+        else rn = v;
+      });
+      double2 Eo[3], Bo[3];
+      if constexpr (src_is_pstd(SRC)) {
+        pstd_update_mode<SRC>(it.kx, 0.0, kz, dt, ph.c, ph.eps0, it.P->inv_n, E, B, J, Eo, Bo);
+      } else {
+        const double K = sqrt(it.kx * it.kx + kz * kz);
+        const Coef q = psatd_coef(K, dt, ph.c, ph.eps0, it.P->inv_n);
+        update_mode<SRC>(it.kx, 0.0, kz, q, ph.c, ph.eps0, dt, E, B, J, ro, rn, Eo, Bo);
+      }
+      static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int comp = Gr::in[Gr::out_slot[o]];
+        if constexpr (comp < 3) held[Gr::out_slot[o]][m] = d2f(Eo[comp]);
+        else held[Gr::out_slot[o]][m] = d2f(Bo[comp - 3]);
+      });
     }
-    static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
-      constexpr int o = decltype(oc)::value;
-      constexpr int comp = Gr::in[Gr::out_slot[o]];
-      if constexpr (comp < 3) held[Gr::out_slot[o]][m] = d2f(Eo[comp]);
-      else held[Gr::out_slot[o]][m] = d2f(Bo[comp - 3]);
-    });
-    // keep the modes' updates from being interleaved (register pressure)
-    __builtin_amdgcn_sched_barrier(0);
   }
 
   // inverse transforms of the outputs, written over their inputs
-  static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
-    constexpr int o = decltype(oc)::value;
-    constexpr int slot = Gr::out_slot[o];
-    double2 v[NP];
+  __device__ __forceinline__ void inverse_store(const ZItem<L>& it, double2* region) {
+    static_for<0, Gr::nout>([&](auto oc) __attribute__((always_inline)) {
+      constexpr int o = decltype(oc)::value;
+      constexpr int slot = Gr::out_slot[o];
+      double2 v[NP];
 #pragma unroll
-    for (int m = 0; m < NP; ++m) v[m] = f2d(held[slot][m]);
-    wfft::fft<L, 1>(v, region, g, s, tw);
-    if (active) {
-      float2* dst = base + Gr::in[slot] * cs;
+      for (int m = 0; m < NP; ++m) v[m] = f2d(held[slot][m]);
+      wfft::fft<L, 1>(v, region, it.g, it.s, it.tw);
+      if (it.active) {
+        float2* dst = it.base + Gr::in[slot] * it.cs;
 #pragma unroll
-      for (int m = 0; m < NP; ++m) dst[loff + S * m] = d2f(v[m]);
-    }
-  });
-}
+        for (int m = 0; m < NP; ++m) dst[it.loff + ZItem<L>::S * m] = d2f(v[m]);
+      }
+    });
+  }
+};
 
 template <int L, int SRC>
 __device__ __forceinline__ void z_item(const PatchDev* P, const WorkItem& wi, float* ws,
                                        const Physics& ph, double2* region, int lane) {
-  z_group<L, SRC, 0>(P, wi, ws, ph, region, lane);
-  z_group<L, SRC, 1>(P, wi, ws, ph, region, lane);
+  const ZItem<L> it(P, wi, ws, lane);
+  ZSet<L, SRC, 0> s0;
+  ZSet<L, SRC, 1> s1;
+  s0.load(it);
+  s0.forward_update(it, ph, region);
+  // at 8 points per lane the second set's loads are in flight during the
+  // first set's inverse transforms; at 12 the registers are not there
+  if constexpr (wfft::Line<L>::P <= 8) s1.load(it);
+  s0.inverse_store(it, region);
+  if constexpr (wfft::Line<L>::P > 8) s1.load(it);
+  s1.forward_update(it, ph, region);
+  s1.inverse_store(it, region);
 }
 
 template <int SRC>

@@ -25,39 +25,57 @@ def test_more_than_one_gpu_is_refused():
 
 def _write_counters(path, counter, rows):
     with open(path, "w", newline="") as f:
-        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Grid_Size",
+                                          "Counter_Name", "Counter_Value"])
         w.writeheader()
-        for name, v in rows:
-            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+        for i, (name, grid, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i + 1, "Kernel_Name": name, "Grid_Size": grid,
+                        "Counter_Name": counter, "Counter_Value": v})
+
+
+def _run(kernels, early, late):
+    """The calibration copy, then trial dispatches at plan time (other grids,
+    value `early`), then six steps of the final plan."""
+    return ([("__amd_rocclr_copyBuffer", 1, None)] + [(k, 7, early[k]) for k in kernels] * 3 +
+            [(k, 9, late[k]) for k in kernels] * 6)
 
 
 def test_traffic_ingest_scales_by_the_calibration_copy(tmp_path, monkeypatch):
     # a 1024 MiB copy reads FETCH = half its size and WRITE = its size: FETCH
-    # is scaled by 2, WRITE by 1; each pass averages over its dispatches
+    # is scaled by 2, WRITE by 1; only the final dispatches count (the
+    # autotuner's trial launches come first), and a pass launched per length
+    # sums its kernels
     kib = 1024 * 1024.0
-    fetch = [("__amd_rocclr_copyBuffer", kib / 2),
-             ("fast2d::x_fwd_kernel(...)", 100.0), ("fast2d::x_fwd_kernel(...)", 300.0),
-             ("fast2d::z_fused_kernel<1, true>(...)", 50.0),
-             ("fast2d::x_inv_kernel(...)", 10.0)]
-    write = [("__amd_rocclr_copyBuffer", kib),
-             ("fast2d::x_fwd_kernel(...)", 40.0), ("fast2d::x_fwd_kernel(...)", 40.0),
-             ("fast2d::z_fused_kernel<1, true>(...)", 5.0),
-             ("fast2d::x_inv_kernel(...)", 1.0)]
+    ks = ["wave2d::(anonymous namespace)::wave_x_kernel<0, 32>(...)",
+          "wave2d::(anonymous namespace)::wave_x_kernel<0, 64>(...)",
+          "wave2d::wave_z_fused_kernel<0>(...)",
+          "wave2d::(anonymous namespace)::wave_x_kernel<1, 32>(...)",
+          "wave2d::(anonymous namespace)::wave_x_kernel<1, 64>(...)"]
+    fetch = _run(ks, {k: 999.0 for k in ks}, dict(zip(ks, (100.0, 300.0, 50.0, 10.0, 20.0))))
+    write = _run(ks, {k: 999.0 for k in ks}, dict(zip(ks, (40.0, 40.0, 5.0, 1.0, 2.0))))
+    fetch[0] = (fetch[0][0], 1, kib / 2)
+    write[0] = (write[0][0], 1, kib)
     fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
     _write_counters(fcsv, "FETCH_SIZE", fetch)
     _write_counters(wcsv, "WRITE_SIZE", write)
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
-    data = bench.ingest_traffic(str(fcsv), str(wcsv), 1, 1024)
-    e = data["2d-4096x4096-sources-1000steps:x_r2c_fwd"]
+    data = bench.ingest_traffic(str(fcsv), str(wcsv), 3, 1024)
+    e = data["2d-256patches-64to512-vacuum-500steps:x_r2c_fwd"]
     assert e["fetch_scale"] == pytest.approx(2.0) and e["write_scale"] == pytest.approx(1.0)
-    assert e["bytes_per_launch"] == pytest.approx((200.0 * 2.0 + 40.0) * 1024.0)
-    assert e["dispatches"] == 2
+    assert e["bytes_per_launch"] == pytest.approx(((100.0 + 300.0) * 2.0 + 80.0) * 1024.0)
     assert e["source_hash"] == bench.kernel_source_hash()
     assert json.loads(out.read_text()) == data
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
-    assert bench.measured_traffic("2d-4096x4096-sources-1000steps", "z_fused") == \
+    assert bench.measured_traffic("2d-256patches-64to512-vacuum-500steps", "z_fused") == \
         pytest.approx((50.0 * 2.0 + 5.0) * 1024.0)
+    assert bench.measured_traffic("2d-256patches-64to512-vacuum-500steps", "x_c2r_inv") == \
+        pytest.approx((30.0 * 2.0 + 3.0) * 1024.0)
+
+
+def test_final_dispatches_skip_the_autotuner_trials():
+    rows = [("a", 1), ("b", 4), ("a", 2), ("b", 4), ("c", 5),   # trials
+            ("a", 2), ("b", 3), ("c", 8), ("a", 2), ("b", 3), ("c", 8)]
+    assert bench.final_dispatches(rows) == rows[5:]
 
 
 def test_plan_grids_parses_the_plan_info():
@@ -77,6 +95,10 @@ def test_kernel_names_map_to_passes():
     assert bench.pass_of_kernel("void psatd::line_pass_kernel<float, 3, 8>(...)") == "y_c2c_inv"
     assert bench.pass_of_kernel("void psatd::fused_z_kernel<float, 2, 0, 2>(...)") == "z_fused"
     assert bench.pass_of_kernel("psatd::fast2d::z_fused_kernel<1, true>(...)") == "z_fused"
+    assert bench.pass_of_kernel("void psatd::ct::ct_line_kernel<float, 1, 96>(...)") == "x_c2r_inv"
+    assert bench.pass_of_kernel("void psatd::wave2d::(anonymous namespace)::wave_x_kernel<0, 128>("
+                                "psatd::PatchDev const*)") == "x_r2c_fwd"
+    assert bench.pass_of_kernel("void psatd::wave2d::wave_z_fused_kernel<0>(...)") == "z_fused"
     assert bench.pass_of_kernel("__amd_rocclr_copyBuffer") is None
 
 
