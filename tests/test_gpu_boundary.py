@@ -64,9 +64,16 @@ def test_dtype_mismatch_rejected_by_binding():
         plan.push(E, B)
 
 
-def test_fused_unsupported_size_reports_status():
+def test_fused_plan_takes_plain_z_passes_where_lines_do_not_fit():
+    # FP64 2D holds at most 2048 modes of a z line per workgroup of the fused
+    # pass: a fused plan with nz = 4096 runs the plain z passes instead
+    plan = pk.Plan([pk.Patch(2, (8, 1, 4096), (1.0, 1.0, 1.0), 0.5)], precision="fp64",
+                   path="fused")
+    assert plan.pass_names == ["x_r2c_fwd", "z_c2c_fwd", "update", "z_c2c_inv", "x_c2r_inv"]
+    plan.close()
+    # a length the planner does not take at all is still an error
     with pytest.raises(pk.PsatdError) as ei:
-        pk.Plan([pk.Patch(2, (8, 1, 4096), (1.0, 1.0, 1.0), 0.5)], precision="fp64", path="fused")
+        pk.Plan([pk.Patch(2, (8, 1, 8192), (1.0, 1.0, 1.0), 0.5)], precision="fp64", path="fused")
     assert ei.value.status == -2
 
 
