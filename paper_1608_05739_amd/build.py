@@ -18,8 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpsatd.so")
-SOURCES = ["kernels.hip", "fast2d.hip", "wave2d.hip", "wavex.hip", "domain.hip", "fdtd.hip",
-           "api.cpp"]
+SOURCES = ["kernels.hip", "fast2d.hip", "wave2d.hip", "wavex.hip", "wave3d.hip", "domain.hip",
+           "fdtd.hip", "api.cpp"]
 
 ARCH = os.environ.get("PSATD_OFFLOAD_ARCH", "gfx950")
 

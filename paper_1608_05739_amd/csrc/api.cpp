@@ -738,12 +738,12 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
       continue;
     }
     if (ps.type == kWaveZ) {
-      if (P.ndim != 2 || !wave2d::z_supported(P.nz))
+      if (P.ndim == 2 ? !wave2d::z_supported(P.nz) : !wave2d::z3_supported(P.nz))
         return fail(PSATD_ERR_STATE, "z_fused (wave): z length not compiled");
-      if (w.count < 1 || w.first < 0 || w.first + w.count > P.mx ||
+      if (w.count < 1 || w.first < 0 || w.first + w.count > P.mx * P.ny ||
           w.count > wave2d::z_lines_per_item(P.nz))
         return fail(PSATD_ERR_STATE, "z_fused (wave): item out of range");
-      if (wave2d::z_region(P.nz) > ps.region ||
+      if ((P.ndim == 2 ? wave2d::z_region(P.nz) : wave2d::z3_region(P.nz)) > ps.region ||
           static_cast<size_t>(ps.region) * wave2d::kWavesPerBlock * sizeof(double2) > ps.shape.lds_bytes)
         return fail(PSATD_ERR_STATE, "z_fused (wave): LDS region too small");
       if (ps.shape.block != wave2d::kBlock)
@@ -871,15 +871,21 @@ Pass make_fast_pass(PassType type, const psatd_plan_s* plan, const std::vector<i
   return ps;
 }
 
-// Wave-resident fused z pass (wave2d.hip): 2D, FP32 storage, the vacuum
-// forms, every z length compiled.
+// Wave-resident fused z pass: 2D (wave2d.hip) in the vacuum forms, 3D
+// (wave3d.hip) in the PSATD forms; FP32 storage, every z length compiled.
 bool wave_z_eligible(const psatd_plan_s* plan) {
   const psatd_config& c = plan->cfg;
   if (c.flags & PSATD_FLAG_GENERIC_KERNELS) return false;
-  if (plan->ndim != 2 || c.precision != PSATD_FP32 || c.path != PSATD_PATH_FUSED) return false;
-  if (plan->src_form != kVacuum && plan->src_form != kPstdVacuum) return false;
+  if (c.precision != PSATD_FP32 || c.path != PSATD_PATH_FUSED) return false;
+  if (plan->ndim == 2) {
+    if (plan->src_form != kVacuum && plan->src_form != kPstdVacuum) return false;
+    for (const PatchDev& P : plan->host_patches)
+      if (!wave2d::z_supported(P.nz)) return false;
+    return true;
+  }
+  if (src_is_pstd(plan->src_form)) return false;
   for (const PatchDev& P : plan->host_patches)
-    if (!wave2d::z_supported(P.nz)) return false;
+    if (!wave2d::z3_supported(P.nz)) return false;
   return true;
 }
 
@@ -893,9 +899,10 @@ Pass make_wave_z_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
   for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
     const PatchDev& P = plan->host_patches[pi];
     const int G = wave2d::z_lines_per_item(P.nz);
-    for (int l = 0; l < P.mx; l += G)
-      items.push_back(WorkItem{static_cast<int>(pi), l, std::min(G, P.mx - l), -1});
-    ps.region = std::max(ps.region, wave2d::z_region(P.nz));
+    const int nlines = P.mx * P.ny;
+    for (int l = 0; l < nlines; l += G)
+      items.push_back(WorkItem{static_cast<int>(pi), l, std::min(G, nlines - l), -1});
+    ps.region = std::max(ps.region, P.ndim == 2 ? wave2d::z_region(P.nz) : wave2d::z3_region(P.nz));
     ps.lines = std::max(ps.lines, G);
     const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
     bytes += (plan->nin + 6) * cells * plan->elem;
@@ -970,8 +977,11 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
       });
       break;
     case kWaveZ:
-      e = wave2d::launch_z_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
-                                 ps.nitems, ws, ph, ps.region);
+      e = plan->ndim == 2
+              ? wave2d::launch_z_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
+                                       ps.nitems, ws, ph, ps.region)
+              : wave2d::launch_z3_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
+                                        ps.nitems, ws, ph, ps.region);
       break;
     case kFastXFwd:
       e = fast2d::launch_x_fwd(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, ws);
@@ -1560,6 +1570,7 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
         if (e == hipSuccess) e = fast2d::configure_attributes();
         if (e == hipSuccess) e = wave2d::configure_attributes();
         if (e == hipSuccess) e = wave2d::configure_x_attributes();
+        if (e == hipSuccess) e = wave2d::configure_z3_attributes();
         if (e != hipSuccess) return hip_fail(e, "kernel attributes");
         if (lookup_scratch(device) != PSATD_OK)
           return fail(PSATD_ERR_HIP, "hipGetSymbolAddress(scratch) failed");

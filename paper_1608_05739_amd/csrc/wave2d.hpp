@@ -28,6 +28,20 @@ hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
 
 hipError_t configure_attributes();
 
+// Fused z pass over 3D patches (wave3d.hip), PSATD forms (src kVacuum, kRho,
+// kJForm), nz in z3_supported: per work item one wavefront transforms the
+// z lines [first, first + count) of the [kx][y][z] spectra of every input,
+// accumulates the six outputs and transforms them back over E and B.
+// region = double2 elements per wave (z3_region(nz) for the plan's lengths).
+bool z3_supported(int nz);
+// double2 elements of one wavefront's LDS in the 3D pass: the exchange region
+// and the per-mode coefficients.
+int z3_region(int nz);
+hipError_t launch_z3_fused(int src, const LaunchShape& sh, hipStream_t stream,
+                           const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
+                           Physics ph, int region);
+hipError_t configure_z3_attributes();
+
 // x passes over 2D patches (wavex.hip): a workgroup transforms a tile of
 // x_rows_per_item(L) consecutive rows of one component (L = nx / 2, the
 // complex row length).  kind: kXFwd (rows -> [kx][z] spectra) or kXInv.

@@ -211,6 +211,31 @@ def test_wave_x_passes_every_row_length(shape, path):
     assert err < TOL["fp32"]
 
 
+# ----------------------------------------------------------------- wave-resident 3D z pass
+# 3D FP32 fused plans with z lines of 32 to 512 points run the wave-resident z
+# pass (outputs accumulated input by input); every compiled length, line
+# counts that leave a partial last item, all three PSATD forms.
+@pytest.mark.parametrize("shape", [(32, 6, 12), (64, 4, 8), (128, 2, 6), (256, 2, 4),
+                                   (512, 4, 2)])
+@pytest.mark.parametrize("form", ["rho", "J", "vacuum"])
+def test_wave_z3_every_length_and_form(shape, form):
+    import paper_1608_05739_amd as pk
+    if form == "vacuum":
+        w = fixtures.workload(4, shape=shape, steps=4)
+        w.sources = False
+    else:
+        w = _w(2, shape, 4)
+    mode = {"rho": "rho", "J": "j", "vacuum": "vacuum"}[form]
+    plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused")
+    info = plan.info
+    plan.close()
+    assert [ln for ln in info.splitlines() if "z_fused" in ln][0].endswith("kernel=wave"), info
+    say(f"wave z 3d {shape} {form}")
+    err = compare(run_gpu(w, "fp32", "fused", w.steps, form=form if form != "vacuum" else "rho"),
+                  run_oracle(w, "fp32", w.steps, form=form if form != "vacuum" else "rho"))
+    assert err < TOL["fp32"]
+
+
 # ----------------------------------------------------------------- batched patches
 def test_batched_patches_workload3_subset():
     w = fixtures.workload(3, npatches=24, steps=3)
