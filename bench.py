@@ -383,7 +383,7 @@ def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
     mode = "rho" if w.sources else "vacuum"
     dom = pk.Domain(len(p.shape), (p.nx, p.ny, p.nz), parts, (guard, guard, guard), p.d, p.dt,
                     precision="fp32", source_mode=mode, order=order, centered_stencil=True,
-                    graph=True)
+                    graph=True, autotune=True)
     npatch, local = dom.local_shape
     plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", order=order,
                    centered_stencil=True, graph=True, autotune=True)

@@ -237,11 +237,13 @@ const char* psatd_last_error(void);
  * A periodic global grid is split into parts[0] x parts[1] x parts[2] boxes of
  * n[a] / parts[a] cells.  Each box, extended by guard[a] cells on both sides of
  * every split axis (parts[a] > 1), is one periodic patch of an internal batched
- * plan; its side box + 2 guard must be an even 2^a 3^b <= 4096.  Each step of
- * psatd_domain_push: fill every patch, interior and guards, from the global
- * fields at the periodic global positions (the guard exchange: copies of the
- * neighbours' current values; sources likewise), advance all patches one step,
- * and write each patch's interior back to its box of the global E and B.
+ * plan; its side box + 2 guard must be an even 2^a 3^b <= 4096, and the x
+ * guard even.  Each step of psatd_domain_push is one step of that plan, whose
+ * forward x pass reads every patch, interior and guards, straight from the
+ * global fields at the periodic global positions (the guard exchange: the
+ * neighbours' current values; sources likewise), and whose inverse x pass
+ * writes each patch's interior straight back to its box of the global E and
+ * B.  No local copy of the fields is made.
  * The guard cells introduce the truncation error; use order p > 0 with
  * PSATD_FLAG_CENTERED_STENCIL for operators that stay local.
  * ------------------------------------------------------------------------- */
@@ -258,9 +260,11 @@ typedef struct {
 } psatd_domain_desc;
 
 /* Build the decomposition and its internal plan (same config; the config's
- * flags apply to it).  Allocates the local patches (the plan's component count
- * x patches x local cells) and the plan's workspace.  Errors as psatd_plan;
- * PSATD_ERR_UNSUPPORTED_SIZE if a local side is not a supported length. */
+ * flags apply to it; its x passes are the generic kernels, which read and
+ * write through the patches' places in the global grid).  Allocates the
+ * plan's workspace.  Errors as psatd_plan; PSATD_ERR_UNSUPPORTED_SIZE if a
+ * local side is not a supported length; PSATD_ERR_INVALID_ARG for an odd x
+ * guard on a split x axis. */
 psatd_status psatd_domain_create(const psatd_config* config, const psatd_domain_desc* domain,
                                  int32_t device, psatd_domain_t* out);
 

@@ -386,7 +386,7 @@ class Domain:
 
     def __init__(self, ndim, n, parts, guard, d, dt, *, precision="fp32", source_mode="vacuum",
                  path="fused", order=0, c=1.0, eps0=1.0, centered_stencil=False, graph=False,
-                 device=0):
+                 autotune=False, device=0):
         self._lib = load_library()
         self._dom = None
         desc = DomainDesc()
@@ -397,7 +397,7 @@ class Domain:
         desc.d = (ctypes.c_double * 3)(*[float(v) for v in d])
         desc.dt = float(dt)
         cfg = make_config(precision, source_mode, path, order, c, eps0, graph=graph,
-                          centered_stencil=centered_stencil)
+                          autotune=autotune, centered_stencil=centered_stencil)
         handle = ctypes.c_void_p()
         _check(self._lib, self._lib.psatd_domain_create(ctypes.byref(cfg), ctypes.byref(desc),
                                                          int(device), ctypes.byref(handle)))

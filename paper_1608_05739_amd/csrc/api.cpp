@@ -218,6 +218,9 @@ struct psatd_plan_s {
   // table addresses point into this host block and are never dereferenced
   bool dry = false;
   std::vector<char> dry_tables;
+  // guard-cell decomposition: each patch's place in the global grid (empty
+  // for ordinary plans); the x passes then read and write the global fields
+  std::vector<GlobalMap> maps;
 };
 
 namespace {
@@ -390,6 +393,7 @@ int tile_period(int kind, const PatchDev& P) {
 bool ct_line_eligible(int kind, const psatd_plan_s* plan) {
   // (PSATD_FLAG_RADIX4_LINES asks for the generic radix-4 schedule)
   if (plan->cfg.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
+  if (!plan->maps.empty() && (kind == kXFwd || kind == kXInv)) return false;  // (see GlobalMap)
   for (const PatchDev& P : plan->host_patches) {
     int nlines, L;
     line_geometry(kind, P, &nlines, &L);
@@ -456,6 +460,7 @@ Pass make_ct_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int
 bool wave_x_eligible(const psatd_plan_s* plan) {
   const psatd_config& c = plan->cfg;
   if (c.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
+  if (!plan->maps.empty()) return false;  // (see GlobalMap)
   if (plan->ndim != 2 || c.precision != PSATD_FP32) return false;
   for (const PatchDev& P : plan->host_patches)
     if (!wave2d::x_supported(P.mx)) return false;
@@ -827,6 +832,7 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
 bool fast2d_eligible(const psatd_plan_s* plan) {
   const psatd_config& c = plan->cfg;
   if (c.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_PSTD)) return false;
+  if (!plan->maps.empty()) return false;  // only the generic x passes read through a map
   if (plan->ndim != 2 || c.precision != PSATD_FP32 || c.path != PSATD_PATH_FUSED) return false;
   for (const PatchDev& P : plan->host_patches)
     if (P.nx != fast2d::kNX || P.nz != fast2d::kNZfast) return false;
@@ -1401,6 +1407,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
     P.kz = reinterpret_cast<const double*>(T + pt[i].kz);
     P.kz_b = reinterpret_cast<const double*>(T + pt[i].kz_b);
     P.post = reinterpret_cast<const double2*>(T + pt[i].post);
+    if (!plan->maps.empty()) P.map = plan->maps[i];
     auto fill = [&](FFTPlanDev& f, int L, int max_radix) {
       const std::vector<int> r = radix_plan(L, max_radix);
       f.n = L;
@@ -1542,13 +1549,8 @@ psatd_status build_plan(psatd_plan_s* plan) {
   return PSATD_OK;
 }
 
-}  // namespace
-
-// ====================================================================== C ABI
-extern "C" {
-
-psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t npatches,
-                        int32_t device, psatd_plan_t* out) {
+psatd_status create_plan(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t npatches,
+                         int32_t device, const GlobalMap* maps, psatd_plan_t* out) {
   try {
     if (!out) return fail(PSATD_ERR_INVALID_ARG, "out is NULL");
     psatd_status st = validate(cfg, patches, npatches);
@@ -1588,6 +1590,7 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
         plan->num_cus = ncu;
     }
     plan->desc.assign(patches, patches + npatches);
+    if (maps) plan->maps.assign(maps, maps + npatches);
     st = build_plan(plan);
     if (st != PSATD_OK) {
       free_plan_memory(plan);
@@ -1601,6 +1604,26 @@ psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches
   } catch (...) {
     return fail(PSATD_ERR_INVALID_ARG, "unexpected host exception");
   }
+}
+
+}  // namespace
+
+// A plan whose patches are boxes of a guard-cell decomposition of one global
+// grid (domain.hip): the x passes read each patch from the global fields and
+// write its interior back (GlobalMap).  maps[i] describes patches[i].
+psatd_status plan_mapped(const psatd_config* cfg, const psatd_patch_desc* patches,
+                         const GlobalMap* maps, int32_t npatches, int32_t device,
+                         psatd_plan_t* out) {
+  if (!maps) return fail(PSATD_ERR_INVALID_ARG, "maps is NULL");
+  return create_plan(cfg, patches, npatches, device, maps, out);
+}
+
+// ====================================================================== C ABI
+extern "C" {
+
+psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t npatches,
+                        int32_t device, psatd_plan_t* out) {
+  return create_plan(cfg, patches, npatches, device, nullptr, out);
 }
 
 psatd_status psatd_plan_describe(const psatd_config* cfg, const psatd_patch_desc* patches,

@@ -30,6 +30,20 @@ struct FFTPlanDev {
   const double2* tw;
 };
 
+// A patch of a guard-cell domain decomposition (map.on != 0): the x passes
+// read its cells straight from the periodic global grid, local cell
+// (x, y, z) at global ((ox + x) mod gnx, (oy + y) mod gny, (oz + z) mod gnz),
+// and write back only its interior [ix0, ix1) x [iy0, iy1) x [iz0, iz1)
+// (local coordinates) -- the guard exchange and the gather of the
+// decomposition, folded into the passes.  ox and ix0, ix1 are even, so the
+// complex pairs (x[2j], x[2j + 1]) of a row never straddle the wrap.
+struct GlobalMap {
+  int on;
+  int gnx, gny, gnz;
+  int ox, oy, oz;
+  int ix0, ix1, iy0, iy1, iz0, iz1;
+};
+
 // One periodic patch.  Real arrays are [nz][ny][nx] (ny = 1 in 2D).  The
 // workspace holds, per patch, one block of comp_stride complex elements per
 // input component; after the x pass the x axis is halved to mx = nx/2 complex
@@ -62,6 +76,7 @@ struct PatchDev {
   FFTPlanDev fx;          // length mx
   FFTPlanDev fy;          // length ny (3D)
   FFTPlanDev fz;          // length nz
+  GlobalMap map;          // guard-cell decomposition: where the patch sits in a global grid
 };
 
 // A unit of work: `count` consecutive lines starting at `first` of component

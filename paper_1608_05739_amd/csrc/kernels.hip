@@ -177,6 +177,22 @@ __device__ __forceinline__ void fft_lds_r4(double2* lds, int nl, int LS, const F
   for (; b > 0; --b, Ns *= 3) lds_stage<3, SIGN, 4>(lds, L, nl, LS, Ns, f->tw);
 }
 
+// Pair j of local row r of a mapped patch (GlobalMap) in the global grid,
+// in complex-pair units; `interior` tells whether the cell belongs to the
+// patch's interior.
+__device__ __forceinline__ long long mapped_pair(const PatchDev* P, int r, int j, bool* interior) {
+  const GlobalMap& m = P->map;
+  int lz, ly;
+  udivmod(r, P->ny, lz, ly);
+  const int gz = (m.oz + lz) % m.gnz;
+  const int gy = (m.oy + ly) % m.gny;
+  const int gx2 = (m.ox / 2 + j) % (m.gnx / 2);
+  if (interior)
+    *interior = lz >= m.iz0 && lz < m.iz1 && ly >= m.iy0 && ly < m.iy1 && 2 * j >= m.ix0 &&
+                2 * j < m.ix1;
+  return (static_cast<long long>(gz) * m.gny + gy) * (m.gnx / 2) + gx2;
+}
+
 template <typename S, int KIND, int PPT>
 __global__ void __launch_bounds__(kLineBlockMax)
 line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
@@ -233,6 +249,17 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
           if (w.hi < nl) r[t] = spec[yline_start(P, l0 + w.hi) + w.lo];
           w.next();
         }
+      } else if (KIND == kXFwd && P->map.on) {
+        // a patch of a decomposition: its rows straight from the global grid
+        const V* src = reinterpret_cast<const V*>(field_ptr(fields, wi.comp));
+#pragma unroll
+        for (int t = 0; t < PPT; ++t) {
+          const int idx = threadIdx.x + t * T;
+          if (idx < total) {
+            const int line = idx / L;
+            r[t] = src[mapped_pair(P, l0 + line, idx - line * L, nullptr)];
+          }
+        }
       } else {
         // x rows (real pairs) or z lines: the tile is contiguous
         const V* src = KIND == kXFwd
@@ -267,9 +294,19 @@ line_pass_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restric
         spec_out[tile_offset(tm, l0 + r, n)] = from_d2<V>(lds[lpad(r * LS + n)]);
       }
     } else if constexpr (KIND == kXInv) {
-      V* dst = reinterpret_cast<V*>(static_cast<S*>(field_ptr(fields, wi.comp)) + P->off_real);
-      for (Walk2 w(L); w.hi < nl; w.next())
-        dst[(long long)(l0 + w.hi) * L + w.lo] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);
+      if (P->map.on) {
+        // a patch of a decomposition: its interior straight into the global grid
+        V* dst = reinterpret_cast<V*>(field_ptr(fields, wi.comp));
+        for (Walk2 w(L); w.hi < nl; w.next()) {
+          bool inside;
+          const long long gi = mapped_pair(P, l0 + w.hi, w.lo, &inside);
+          if (inside) dst[gi] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);
+        }
+      } else {
+        V* dst = reinterpret_cast<V*>(static_cast<S*>(field_ptr(fields, wi.comp)) + P->off_real);
+        for (Walk2 w(L); w.hi < nl; w.next())
+          dst[(long long)(l0 + w.hi) * L + w.lo] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);
+      }
     } else if constexpr (KIND == kYInv) {
       for (Walk2 w(L); w.hi < nl; w.next())
         spec_out[yline_start(P, l0 + w.hi) + w.lo] = from_d2<V>(lds[lpad(w.hi * LS + w.lo)]);

@@ -126,6 +126,7 @@ def _dom(n=(128, 1, 128), parts=(2, 1, 2), guard=(16, 0, 16), ndim=2):
     (_dom(guard=(5, 0, 16)), -2),            # 64 + 2 * 5 = 74 = 2 * 37: unsupported length
     (_dom(parts=(3, 1, 2)), -1),             # 128 does not split into 3 equal boxes
     (_dom(guard=(-1, 0, 16)), -1),           # negative guard
+    (_dom(guard=(49, 0, 16)), -1),           # 64 + 2 * 49 = 162 is supported, but the x guard is odd
     (_dom(n=(128, 2, 128)), -1),             # 2D with ny != 1
     (_dom(ndim=4), -1),
 ])
