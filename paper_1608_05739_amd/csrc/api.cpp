@@ -455,20 +455,53 @@ Pass make_ct_line_pass(int kind, const psatd_plan_s* plan, const std::vector<int
   return ps;
 }
 
-// Wave-resident x passes (wavex.hip): 2D, FP32 storage, every row length
-// compiled.  (PSATD_FLAG_RADIX4_LINES asks for the generic radix-4 schedule.)
+// Wave-resident x passes (wavex.hip): 2D or 3D, FP32 storage, every row
+// length compiled.  (PSATD_FLAG_RADIX4_LINES asks for the generic radix-4
+// schedule.)
 bool wave_x_eligible(const psatd_plan_s* plan) {
   const psatd_config& c = plan->cfg;
   if (c.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
   if (!plan->maps.empty()) return false;  // (see GlobalMap)
-  if (plan->ndim != 2 || c.precision != PSATD_FP32) return false;
+  if (c.precision != PSATD_FP32) return false;
   for (const PatchDev& P : plan->host_patches)
     if (!wave2d::x_supported(P.mx)) return false;
   return true;
 }
 
-// Work items of x_rows_per_item(L) consecutive rows of one component, one
-// launch per row length.
+// Wave-resident y passes (wavex.hip): 3D, FP32 storage, every y length
+// compiled.
+bool wave_y_eligible(const psatd_plan_s* plan) {
+  const psatd_config& c = plan->cfg;
+  if (c.flags & (PSATD_FLAG_GENERIC_KERNELS | PSATD_FLAG_RADIX4_LINES)) return false;
+  if (plan->ndim != 3 || c.precision != PSATD_FP32) return false;
+  for (const PatchDev& P : plan->host_patches)
+    if (!wave2d::x_supported(P.ny)) return false;
+  return true;
+}
+
+bool wave_line_eligible(int kind, const psatd_plan_s* plan) {
+  if (kind == kXFwd || kind == kXInv) return wave_x_eligible(plan);
+  if (kind == kYFwd || kind == kYInv) return wave_y_eligible(plan);
+  return false;
+}
+
+// Line length, lines, and the run of lines a tile stays in, of the
+// wave-resident x and y passes: x rows (L = nx / 2) in runs of nz (2D) or ny
+// (3D) rows; y lines (L = ny) l = kx nz + z in runs of nz.
+void wave_line_geometry(int kind, const PatchDev& P, int* L, int* nlines, int* run) {
+  if (kind == kYFwd || kind == kYInv) {
+    *L = P.ny;
+    *nlines = P.mx * P.nz;
+    *run = P.nz;
+  } else {
+    *L = P.mx;
+    *nlines = P.ny * P.nz;
+    *run = P.ndim == 2 ? P.nz : P.ny;
+  }
+}
+
+// Work items of up to x_rows_per_item(L) consecutive lines of one component
+// inside one run (wave_line_geometry), one launch per line length.
 Pass make_wave_x_pass(int kind, const psatd_plan_s* plan, const std::vector<int>& comps,
                       std::vector<WorkItem>& items) {
   Pass ps;
@@ -478,8 +511,13 @@ Pass make_wave_x_pass(int kind, const psatd_plan_s* plan, const std::vector<int>
   const size_t first = items.size();
   double bytes = 0.0;
   std::set<int> lengths;
-  for (const PatchDev& P : plan->host_patches) lengths.insert(P.mx);
+  for (const PatchDev& P : plan->host_patches) {
+    int L, nl, run;
+    wave_line_geometry(kind, P, &L, &nl, &run);
+    lengths.insert(L);
+  }
   size_t lds = 0;
+  int block = 64;
   for (int L : lengths) {
     SubLaunch sub;
     sub.L = L;
@@ -487,23 +525,26 @@ Pass make_wave_x_pass(int kind, const psatd_plan_s* plan, const std::vector<int>
     const int T = wave2d::x_rows_per_item(L);
     for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
       const PatchDev& P = plan->host_patches[pi];
-      if (P.mx != L) continue;
+      int Lp, nrows, A;
+      wave_line_geometry(kind, P, &Lp, &nrows, &A);
+      if (Lp != L) continue;
       for (int c : comps)
-        for (int z = 0; z < P.nz; z += T)
-          items.push_back(WorkItem{static_cast<int>(pi), z, std::min(T, P.nz - z), c});
+        for (int r0 = 0; r0 < nrows; r0 += A)
+          for (int a = 0; a < A; a += T)
+            items.push_back(WorkItem{static_cast<int>(pi), r0 + a, std::min(T, A - a), c});
       const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
       bytes += comps.size() * 2.0 * cells * plan->elem;
     }
     sub.nitems = static_cast<int>(items.size() - first) - sub.first;
-    const size_t sub_lds =
-        static_cast<size_t>(wave2d::z_region(L)) * wave2d::kWavesPerBlock * sizeof(double2);
-    sub.shape = LaunchShape{sub.nitems, wave2d::kBlock, sub_lds};
+    const size_t sub_lds = wave2d::x_lds(L);
+    sub.shape = LaunchShape{sub.nitems, wave2d::x_block(L), sub_lds};
     lds = std::max(lds, sub_lds);
+    block = std::max(block, wave2d::x_block(L));
     ps.lines = std::max(ps.lines, T);
     ps.subs.push_back(sub);
   }
   ps.nitems = static_cast<int>(items.size() - first);
-  ps.shape = LaunchShape{ps.nitems, wave2d::kBlock, lds};
+  ps.shape = LaunchShape{ps.nitems, block, lds};
   ps.bytes = bytes;
   ps.comps = comps;
   ps.d_items = reinterpret_cast<WorkItem*>(first);
@@ -724,20 +765,20 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
       continue;
     }
     if (ps.type == kWaveX) {
-      if (P.ndim != 2 || !wave2d::x_supported(P.mx))
-        return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): row length not compiled");
+      int L, nrows, A;
+      wave_line_geometry(ps.line_kind, P, &L, &nrows, &A);
+      if (!wave2d::x_supported(L) || ((ps.line_kind == kYFwd || ps.line_kind == kYInv) && P.ndim != 3))
+        return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): line length not compiled");
       if (w.comp < 0 || w.comp >= plan->nin)
         return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): bad component");
-      if (w.count < 1 || w.first < 0 || w.first + w.count > P.nz ||
-          w.count > wave2d::x_rows_per_item(P.mx))
+      if (w.count < 1 || w.first < 0 || w.first + w.count > nrows ||
+          w.count > wave2d::x_rows_per_item(L) || w.first / A != (w.first + w.count - 1) / A)
         return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): item out of range");
       bool in_sub = false;
       for (const SubLaunch& sub : ps.subs)
         in_sub = in_sub ||
-                 (i >= sub.first && i < sub.first + sub.nitems && sub.L == P.mx &&
-                  sub.shape.block == wave2d::kBlock &&
-                  sub.shape.lds_bytes >= static_cast<size_t>(wave2d::z_region(P.mx)) *
-                                             wave2d::kWavesPerBlock * sizeof(double2));
+                 (i >= sub.first && i < sub.first + sub.nitems && sub.L == L &&
+                  sub.shape.block == wave2d::x_block(L) && sub.shape.lds_bytes >= wave2d::x_lds(L));
       if (!in_sub)
         return fail(PSATD_ERR_STATE, std::string(ps.name) + " (wave): item outside its length's launch");
       continue;
@@ -1225,8 +1266,8 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
       std::vector<WorkItem> its;
       add_cand(make_ct_line_pass(ps.line_kind, plan, ps.comps, its), its);
     }
-    if (linelike && ps.type != kWaveX && (ps.line_kind == kXFwd || ps.line_kind == kXInv) &&
-        wave_x_eligible(plan) && e == hipSuccess) {
+    if (linelike && ps.type != kWaveX && wave_line_eligible(ps.line_kind, plan) &&
+        e == hipSuccess) {
       std::vector<WorkItem> its;
       add_cand(make_wave_x_pass(ps.line_kind, plan, ps.comps, its), its);
     }
@@ -1473,8 +1514,7 @@ psatd_status build_plan(psatd_plan_s* plan) {
     // compile-time line kernels where every length is compiled, else the
     // generic ones (the autotuner times both)
     auto line = [&](int kind, const std::vector<int>& comps) {
-      if ((kind == kXFwd || kind == kXInv) && wave_x_eligible(plan))
-        return make_wave_x_pass(kind, plan, comps, items);
+      if (wave_line_eligible(kind, plan)) return make_wave_x_pass(kind, plan, comps, items);
       return ct_line_eligible(kind, plan) ? make_ct_line_pass(kind, plan, comps, items)
                                           : make_line_pass(kind, plan, comps, items);
     };

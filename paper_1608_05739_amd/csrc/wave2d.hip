@@ -192,7 +192,7 @@ bool z_supported(int nz) {
 
 int z_lines_per_item(int nz) { return 64 / (nz / wfft::points(nz)); }
 
-int z_region(int nz) { return z_lines_per_item(nz) * (nz + nz / 8); }
+int z_region(int nz) { return z_lines_per_item(nz) * wfft::stride_of(nz); }
 
 hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
                           const PatchDev* patches, const WorkItem* items, int nitems, void* ws,

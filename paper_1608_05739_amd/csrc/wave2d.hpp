@@ -42,13 +42,15 @@ hipError_t launch_z3_fused(int src, const LaunchShape& sh, hipStream_t stream,
                            Physics ph, int region);
 hipError_t configure_z3_attributes();
 
-// x passes over 2D patches (wavex.hip): a workgroup transforms a tile of
-// x_rows_per_item(L) consecutive rows of one component (L = nx / 2, the
-// complex row length).  kind: kXFwd (rows -> [kx][z] spectra) or kXInv.
-// One launch covers the items of patches with nx / 2 = L; the block holds
-// kWavesPerBlock regions of z_region(L) double2 elements of LDS.
+// x passes (wavex.hip): a workgroup of x_block(L) threads transforms a tile
+// of up to x_rows_per_item(L) consecutive rows of one component inside one
+// run of the spectra layout (L = nx / 2, the complex row length).  kind:
+// kXFwd (rows -> spectra) or kXInv.  One launch covers the items of patches
+// with nx / 2 = L, with x_lds(L) bytes of LDS per workgroup.
 bool x_supported(int L);
 int x_rows_per_item(int L);
+int x_block(int L);     // threads per workgroup
+size_t x_lds(int L);    // bytes of LDS per workgroup
 hipError_t launch_x(int kind, int L, const LaunchShape& sh, hipStream_t stream,
                     const PatchDev* patches, const WorkItem* items, int nitems,
                     const FieldPtrs& fields, void* ws);

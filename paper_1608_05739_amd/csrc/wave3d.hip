@@ -237,7 +237,7 @@ bool z3_supported(int nz) { return nz == 32 || nz == 64 || nz == 128 || nz == 25
 
 int z3_region(int nz) {
   // the exchange region and six FP64 values per mode and lane (in double2)
-  return z_lines_per_item(nz) * (nz + nz / 8) + 6 * wfft::points(nz) * 64 / 2;
+  return z_lines_per_item(nz) * wfft::stride_of(nz) + 6 * wfft::points(nz) * 64 / 2;
 }
 
 hipError_t launch_z3_fused(int src, const LaunchShape& sh, hipStream_t stream,

@@ -2,9 +2,13 @@
 // arithmetic): the r2c transform of the field rows into the [kx][z] spectra
 // and the c2r transform back.
 //
-// A workgroup of kWavesPerBlock wavefronts takes a tile of T = 4 G
-// consecutive rows z of one component of one patch (G rows per wave, as the
-// wave-resident FFT lays them out: lane s of row g holds points s + S m).
+// A workgroup of W wavefronts takes a tile of T = W G consecutive rows of one
+// component of one patch (G rows per wave, as the wave-resident FFT lays them
+// out: lane s of row g holds points s + S m; W = 8 where G <= 2, else 4, so
+// that T >= 16 rows: runs of 128 bytes in the crossing, FP32).
+// Row r of a patch is z in 2D and z ny + y in 3D; a tile never leaves its
+// run of A = nz (2D) or ny (3D) rows, and column kx of row r = p A + a sits at
+// p mx A + kx A + a of the spectra ([kx][z] in 2D, [z][kx][y] in 3D).
 // Each wave transforms its rows in registers with exchanges through its own
 // LDS region (wfft.hpp, no workgroup barrier inside the transform).  The
 // spectra are column-major ([kx][z]), so the tile crosses the workgroup once
@@ -38,11 +42,23 @@ __device__ __forceinline__ float2 d2f(double2 v) {
 template <int L>
 struct XTile {
   static constexpr int G = wfft::Line<L>::G;
-  static constexpr int T = kWavesPerBlock * G;
+  static constexpr int W = G <= 2 ? 8 : 4;  // waves per workgroup
+  static constexpr int NT = 64 * W;         // threads per workgroup
+  static constexpr int T = W * G;
   static constexpr int ROW = L + 1;
   static_assert(G * ROW <= 2 * wfft::Line<L>::REGION, "staging fits the region");
   static_assert((T & (T - 1)) == 0, "rows per tile a power of two");
 };
+
+// Rows of one run of the spectra layout (see above) and the start of the
+// tile's run in the spectra: p mx A + a0 for the tile's first row p A + a0.
+__device__ __forceinline__ int run_rows(const PatchDev* P) { return P->ndim == 2 ? P->nz : P->ny; }
+__device__ __forceinline__ long long tile_start(const PatchDev* P, int first) {
+  const int A = run_rows(P);
+  int p, a0;
+  udivmod(first, A, p, a0);
+  return static_cast<long long>(p) * P->mx * A + a0;
+}
 
 // Partner index L - k of the r2c split (k = 0 pairs with itself).
 template <int L>
@@ -107,15 +123,16 @@ __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
   // the crossing: T consecutive z of each kx, as runs of T complex values
   float2* const spec = reinterpret_cast<float2*>(ws) + P->off_spec +
                        static_cast<long long>(wi.comp) * P->comp_stride;
-  const int nz = P->nz;
+  const int A = run_rows(P);
+  float2* const dst = spec + tile_start(P, wi.first);
   constexpr int total = XT::T * L;
 #pragma unroll 4
-  for (int idx = tid; idx < total; idx += kBlock) {
+  for (int idx = tid; idx < total; idx += XT::NT) {
     const int zl = idx & (XT::T - 1);
     const int kx = idx / XT::T;
     if (zl < wi.count) {
       const float2* w = reinterpret_cast<const float2*>(lds + (zl / XT::G) * LN::REGION);
-      spec[static_cast<long long>(kx) * nz + wi.first + zl] = w[(zl % XT::G) * XT::ROW + kx];
+      dst[static_cast<long long>(kx) * A + zl] = w[(zl % XT::G) * XT::ROW + kx];
     }
   }
   __syncthreads();  // the regions are reused by the next tile
@@ -140,15 +157,16 @@ __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
   // the crossing: runs of T consecutive z of each kx into the rows' staging
   const float2* const spec = reinterpret_cast<const float2*>(ws) + P->off_spec +
                              static_cast<long long>(wi.comp) * P->comp_stride;
-  const int nz = P->nz;
+  const int A = run_rows(P);
+  const float2* const in = spec + tile_start(P, wi.first);
   constexpr int total = XT::T * L;
 #pragma unroll 4
-  for (int idx = tid; idx < total; idx += kBlock) {
+  for (int idx = tid; idx < total; idx += XT::NT) {
     const int zl = idx & (XT::T - 1);
     const int kx = idx / XT::T;
     if (zl < wi.count) {
       float2* w = reinterpret_cast<float2*>(lds + (zl / XT::G) * LN::REGION);
-      w[(zl % XT::G) * XT::ROW + kx] = spec[static_cast<long long>(kx) * nz + wi.first + zl];
+      w[(zl % XT::G) * XT::ROW + kx] = in[static_cast<long long>(kx) * A + zl];
     }
   }
   __syncthreads();
@@ -184,9 +202,85 @@ __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
   __syncthreads();  // the regions are reused by the next tile
 }
 
-// One kernel per row length and direction; a pass launches one per length.
+// y passes (3D): lines along y, length L = ny.  A tile is T consecutive z
+// of one kx (line l = kx nz + z); the forward pass reads each line from the
+// x pass's [z][kx][y] block and writes runs of T consecutive z per (kx, y)
+// into the [kx][y][z] block of the z passes; the inverse pass the reverse.
+template <int L, int SIGN>
+__device__ void y_tile(const PatchDev* __restrict__ P, const WorkItem& wi, float* __restrict__ ws,
+                       double2* lds) {
+  using LN = wfft::Line<L>;
+  using XT = XTile<L>;
+  constexpr int NP = LN::P;
+  constexpr int S = LN::S;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane / S;
+  const int s = lane % S;
+  double2* const region = lds + wave * LN::REGION;
+  const int row = wave * XT::G + g;
+  const bool active = row < wi.count;
+  const int nz = P->nz;
+  int kx, z0;
+  udivmod(wi.first, nz, kx, z0);
+  const int z = z0 + (active ? row : 0);  // idle rows read a valid line
+  float2* const blk_x = reinterpret_cast<float2*>(ws) + P->off_spec +
+                        static_cast<long long>(wi.comp) * P->comp_stride;
+  float2* const blk_z = reinterpret_cast<float2*>(ws) + P->off_z +
+                        static_cast<long long>(wi.comp) * P->comp_stride;
+  // [z][kx][y]: line (kx, z) at (z mx + kx) L;  [kx][y][z]: (kx, y, z) at (kx L + y) nz + z
+  float2* const yline = blk_x + (static_cast<long long>(z) * P->mx + kx) * L;
+  float2* const zrun = blk_z + static_cast<long long>(kx) * L * nz + z0;
+  wfft::Twiddles<L> tws;
+  tws.load(P->fy.tw, s);
+  constexpr int total = XT::T * L;
+  double2 v[NP];
+  if constexpr (SIGN < 0) {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) v[m] = f2d(yline[s + S * m]);
+    wfft::fft<L, -1>(v, region, g, s, tws);
+    wfft::wave_sync();  // the transform's last reads are done before the staging
+    float2* const stg = reinterpret_cast<float2*>(region);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) stg[g * XT::ROW + s + S * m] = d2f(v[m]);
+    __syncthreads();
+#pragma unroll 4
+    for (int idx = tid; idx < total; idx += XT::NT) {
+      const int zl = idx & (XT::T - 1);
+      const int y = idx / XT::T;
+      if (zl < wi.count) {
+        const float2* w = reinterpret_cast<const float2*>(lds + (zl / XT::G) * LN::REGION);
+        zrun[static_cast<long long>(y) * nz + zl] = w[(zl % XT::G) * XT::ROW + y];
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int idx = tid; idx < total; idx += XT::NT) {
+      const int zl = idx & (XT::T - 1);
+      const int y = idx / XT::T;
+      if (zl < wi.count) {
+        float2* w = reinterpret_cast<float2*>(lds + (zl / XT::G) * LN::REGION);
+        w[(zl % XT::G) * XT::ROW + y] = zrun[static_cast<long long>(y) * nz + zl];
+      }
+    }
+    __syncthreads();
+    const float2* const stg = reinterpret_cast<const float2*>(region) + g * XT::ROW;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) v[m] = f2d(stg[s + S * m]);
+    wfft::wave_sync();  // staged values read before the transform reuses the region
+    wfft::fft<L, 1>(v, region, g, s, tws);
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) yline[s + S * m] = d2f(v[m]);
+    }
+  }
+  __syncthreads();  // the regions are reused by the next tile
+}
+
+// One kernel per line length and pass kind; a pass launches one per length.
 template <int KIND, int L>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(512)
 wave_x_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items, int nitems,
               FieldPtrs fields, float* __restrict__ ws) {
   extern __shared__ double2 lds[];
@@ -194,8 +288,10 @@ wave_x_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__
     const WorkItem wi = items[xcd_local_order(it, nitems)];
     if constexpr (KIND == kXFwd) {
       x_fwd_tile<L>(patches + wi.patch, wi, fields, ws, lds);
-    } else {
+    } else if constexpr (KIND == kXInv) {
       x_inv_tile<L>(patches + wi.patch, wi, fields, ws, lds);
+    } else {
+      y_tile<L, KIND == kYFwd ? -1 : 1>(patches + wi.patch, wi, ws, lds);
     }
   }
 }
@@ -205,7 +301,8 @@ hipError_t launch_kind(int L, const LaunchShape& sh, hipStream_t stream, const P
                        const WorkItem* items, int nitems, const FieldPtrs& f, float* w) {
 #define PSATD_WX_CASE(LEN)                                                                     \
   case LEN:                                                                                    \
-    hipLaunchKernelGGL((wave_x_kernel<KIND, LEN>), dim3(sh.grid), dim3(kBlock), sh.lds_bytes,  \
+    hipLaunchKernelGGL((wave_x_kernel<KIND, LEN>), dim3(sh.grid), dim3(XTile<LEN>::NT),        \
+                       sh.lds_bytes,                                                           \
                        stream, patches, items, nitems, f, w);                                  \
     break;
   switch (L) {
@@ -240,20 +337,36 @@ hipError_t configure_kind() {
 
 bool x_supported(int L) { return z_supported(L); }
 
-int x_rows_per_item(int L) { return kWavesPerBlock * z_lines_per_item(L); }
+int x_waves(int L) { return z_lines_per_item(L) <= 2 ? 8 : 4; }
+
+int x_rows_per_item(int L) { return x_waves(L) * z_lines_per_item(L); }
+
+int x_block(int L) { return 64 * x_waves(L); }
+
+size_t x_lds(int L) {
+  return static_cast<size_t>(x_waves(L)) * z_lines_per_item(L) * wfft::stride_of(L) *
+         sizeof(double2);
+}
 
 hipError_t launch_x(int kind, int L, const LaunchShape& sh, hipStream_t stream,
                     const PatchDev* patches, const WorkItem* items, int nitems,
                     const FieldPtrs& fields, void* ws) {
   float* w = static_cast<float*>(ws);
-  if (kind == kXFwd) return launch_kind<kXFwd>(L, sh, stream, patches, items, nitems, fields, w);
-  if (kind == kXInv) return launch_kind<kXInv>(L, sh, stream, patches, items, nitems, fields, w);
-  return hipErrorInvalidValue;
+  switch (kind) {
+    case kXFwd: return launch_kind<kXFwd>(L, sh, stream, patches, items, nitems, fields, w);
+    case kXInv: return launch_kind<kXInv>(L, sh, stream, patches, items, nitems, fields, w);
+    case kYFwd: return launch_kind<kYFwd>(L, sh, stream, patches, items, nitems, fields, w);
+    case kYInv: return launch_kind<kYInv>(L, sh, stream, patches, items, nitems, fields, w);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t configure_x_attributes() {
-  const hipError_t e = configure_kind<kXFwd>();
-  return e != hipSuccess ? e : configure_kind<kXInv>();
+  const hipError_t r[] = {configure_kind<kXFwd>(), configure_kind<kXInv>(), configure_kind<kYFwd>(),
+                          configure_kind<kYInv>()};
+  for (hipError_t e : r)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
 }
 
 }  // namespace wave2d

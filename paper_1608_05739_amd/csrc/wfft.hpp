@@ -8,7 +8,7 @@
 // w = exp(SIGN 2 pi i / (Ns R)), applies DFT<R> and produces
 // y[(j - k) R + k + q Ns] (Stockham autosort; Ns = product of the radices
 // before the stage).  Between stages the wave exchanges y through its own LDS
-// region (padded by one element every 8) and reads back y[s + S m]; no other
+// region (padded, see kPadShift) and reads back y[s + S m]; no other
 // wave touches that region, so no workgroup barrier is needed.  The last
 // stage's outputs already sit in the input layout (natural order, point
 // s + S m in register m), so input and output are both natural order.
@@ -54,18 +54,23 @@ __host__ __device__ constexpr int points(int L) {
   return (L % 3 == 0) ? 12 : (L == 1024 ? 16 : 8);
 }
 
+// LDS padding: one element every 2^kPadShift (e -> e + (e >> kPadShift)).
+constexpr int kPadShift = 3;
+// Padded LDS elements of one line of length L.
+__host__ __device__ constexpr int stride_of(int L) { return L + (L >> kPadShift); }
+
 template <int L>
 struct Line {
   static constexpr int P = Sched<L>::P;
   static constexpr int S = L / P;                // lanes per line
   static constexpr int G = 64 / S;               // lines per wave
-  static constexpr int STRIDE = L + L / 8;       // padded LDS elements per line
+  static constexpr int STRIDE = stride_of(L);    // padded LDS elements per line
   static constexpr int REGION = G * STRIDE;      // double2 elements per wave region
   static_assert(L % P == 0 && 64 % S == 0 && L % 8 == 0, "wave layout");
 };
 
 // Padded LDS index of logical element e (one pad element every 8).
-__host__ __device__ constexpr int pa(int e) { return e + (e >> 3); }
+__host__ __device__ constexpr int pa(int e) { return e + (e >> kPadShift); }
 
 // Product of the radices before stage i.
 template <int L>

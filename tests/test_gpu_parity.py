@@ -182,9 +182,10 @@ def test_compile_time_line_tiles_split_at_the_tile_map(index, shape, precision):
     plan = pk.Plan(w.patches, precision=precision, source_mode="rho", path="fused")
     info = plan.info
     plan.close()
-    # (2D FP32 plans take the wave-resident x passes; their y and z passes
-    # do not exist or are fused, so only 3D or FP64 plans show the kernels)
-    want = "kernel=wave" if (index == 1 and precision == "fp32") else "kernel=compile-time"
+    # (FP32 plans take the wave-resident x passes, and a 3D FP32 plan shows
+    # the compile-time kernels only in y passes of a compiled length; FP64
+    # plans show them in the x passes)
+    want = "kernel=wave" if precision == "fp32" else "kernel=compile-time"
     assert want in info, info
     say(f"compile-time tiles {shape} {precision}")
     err = compare(run_gpu(w, precision, "fused", w.steps), run_oracle(w, precision, w.steps),
@@ -208,6 +209,26 @@ def test_wave_x_passes_every_row_length(shape, path):
     assert info.count("kernel=wave") >= 2, info
     say(f"wave x passes {shape} fp32 {path}")
     err = compare(run_gpu(w, "fp32", path, w.steps), run_oracle(w, "fp32", w.steps))
+    assert err < TOL["fp32"]
+
+
+# ----------------------------------------------------------------- wave-resident 3D y passes
+# 3D FP32 plans with y lines of a compiled length run the y passes as
+# wave-resident transforms over tiles of consecutive z of one kx; every
+# compiled y length, z counts that leave a partial last tile.
+@pytest.mark.parametrize("shape", [(36, 32, 8), (18, 48, 12), (24, 64, 6), (12, 96, 4),
+                                   (24, 128, 4), (6, 192, 4), (18, 256, 2), (6, 384, 2),
+                                   (12, 512, 2)])
+def test_wave_y_passes_every_line_length(shape):
+    import paper_1608_05739_amd as pk
+    w = _w(2, shape, 3)
+    plan = pk.Plan(w.patches, precision="fp32", source_mode="rho", path="fused")
+    info = plan.info
+    plan.close()
+    ylines = [ln for ln in info.splitlines() if ln.strip().startswith("y_c2c")]
+    assert len(ylines) == 2 and all(ln.endswith("kernel=wave") for ln in ylines), info
+    say(f"wave y passes {shape}")
+    err = compare(run_gpu(w, "fp32", "fused", w.steps), run_oracle(w, "fp32", w.steps))
     assert err < TOL["fp32"]
 
 
