@@ -55,7 +55,7 @@ __host__ __device__ constexpr int points(int L) {
 }
 
 // LDS padding: one element every 2^kPadShift (e -> e + (e >> kPadShift)).
-constexpr int kPadShift = 3;
+constexpr int kPadShift = 4;
 // Padded LDS elements of one line of length L.
 __host__ __device__ constexpr int stride_of(int L) { return L + (L >> kPadShift); }
 
@@ -69,7 +69,7 @@ struct Line {
   static_assert(L % P == 0 && 64 % S == 0 && L % 8 == 0, "wave layout");
 };
 
-// Padded LDS index of logical element e (one pad element every 8).
+// Padded LDS index of logical element e.
 __host__ __device__ constexpr int pa(int e) { return e + (e >> kPadShift); }
 
 // Product of the radices before stage i.
