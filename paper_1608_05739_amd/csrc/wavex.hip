@@ -308,6 +308,7 @@ hipError_t launch_kind(int L, const LaunchShape& sh, hipStream_t stream, const P
   switch (L) {
     PSATD_WX_CASE(32) PSATD_WX_CASE(48) PSATD_WX_CASE(64) PSATD_WX_CASE(96) PSATD_WX_CASE(128)
     PSATD_WX_CASE(192) PSATD_WX_CASE(256) PSATD_WX_CASE(384) PSATD_WX_CASE(512)
+    PSATD_WX_CASE(1024)
     default:
       return hipErrorInvalidValue;
   }
@@ -327,7 +328,7 @@ hipError_t configure_kind() {
                           set_x_lds_limit<KIND, 64>(),  set_x_lds_limit<KIND, 96>(),
                           set_x_lds_limit<KIND, 128>(), set_x_lds_limit<KIND, 192>(),
                           set_x_lds_limit<KIND, 256>(), set_x_lds_limit<KIND, 384>(),
-                          set_x_lds_limit<KIND, 512>()};
+                          set_x_lds_limit<KIND, 512>(), set_x_lds_limit<KIND, 1024>()};
   for (hipError_t e : r)
     if (e != hipSuccess) return e;
   return hipSuccess;
@@ -335,7 +336,7 @@ hipError_t configure_kind() {
 
 }  // namespace
 
-bool x_supported(int L) { return z_supported(L); }
+bool x_supported(int L) { return z_supported(L) || L == 1024; }
 
 int x_waves(int L) { return z_lines_per_item(L) <= 2 ? 8 : 4; }
 

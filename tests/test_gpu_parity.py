@@ -198,7 +198,7 @@ def test_compile_time_line_tiles_split_at_the_tile_map(index, shape, precision):
 # consecutive rows; every compiled row length nx / 2, row counts that leave a
 # partial last tile, both paths, with sources.
 @pytest.mark.parametrize("shape", [(36, 64), (18, 96), (24, 128), (12, 192), (54, 256),
-                                   (6, 384), (72, 512), (6, 768), (18, 1024)])
+                                   (6, 384), (72, 512), (6, 768), (18, 1024), (12, 2048)])
 @pytest.mark.parametrize("path", ["fused", "plain"])
 def test_wave_x_passes_every_row_length(shape, path):
     import paper_1608_05739_amd as pk
@@ -218,7 +218,7 @@ def test_wave_x_passes_every_row_length(shape, path):
 # compiled y length, z counts that leave a partial last tile.
 @pytest.mark.parametrize("shape", [(36, 32, 8), (18, 48, 12), (24, 64, 6), (12, 96, 4),
                                    (24, 128, 4), (6, 192, 4), (18, 256, 2), (6, 384, 2),
-                                   (12, 512, 2)])
+                                   (12, 512, 2), (6, 1024, 2)])
 def test_wave_y_passes_every_line_length(shape):
     import paper_1608_05739_amd as pk
     w = _w(2, shape, 3)
