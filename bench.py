@@ -83,7 +83,8 @@ def pass_of_kernel(name):
     import re
     for key, pname in (("x_fwd_kernel", "x_r2c_fwd"), ("z_fused_kernel", "z_fused"),
                        ("x_inv_kernel", "x_c2r_inv"), ("fused_z_kernel", "z_fused"),
-                       ("wave_z_fused", "z_fused"), ("update_kernel", "update")):
+                       ("wave_z_fused", "z_fused"), ("wave_z3_fused", "z_fused"),
+                       ("update_kernel", "update")):
         if key in name:
             return pname
     m = (re.search(r"(?:line_pass_kernel|ct_line_kernel)<[^,<>]+, ?(\d)", name)
@@ -215,6 +216,29 @@ def device_fields(w, plan, dtype):
     return E, B, J, ro, rn
 
 
+def fp32_plan(pk, args, patches, mode):
+    """The timed plan: FP32 storage, fused path, graph replay, autotuned --
+    or, with --tuning-in, the kernel choices an earlier autotuned run saved
+    (no timing launches at plan time; profilers that serialize dispatches
+    distort the autotuner's timings, so profiled runs reuse a normal run's
+    choices).  --tuning-out saves the plan's choices."""
+    if args.tuning_in:
+        with open(args.tuning_in) as f:
+            text = f.read().strip()
+        plan = pk.Plan(patches, precision="fp32", source_mode=mode, path="fused", graph=True,
+                       tuning=text)
+    else:
+        plan = pk.Plan(patches, precision="fp32", source_mode=mode, path="fused", graph=True,
+                       autotune=True)
+    if args.tuning_out:
+        d = os.path.dirname(args.tuning_out)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.tuning_out, "w") as f:
+            f.write(plan.tuning + "\n")
+    return plan
+
+
 def time_steps(plan, E, B, J, ro, rn, steps, warmup, vacuum_batch):
     """Wall-clock seconds of exactly `steps` steps, synchronized on both sides."""
     import torch
@@ -272,10 +296,11 @@ def summarize(per_patch):
             "pooled": float(np.sqrt(num / max(den, 1e-300)))}
 
 
-def oracle_leg(w, budget_s, gpu_results, steps):
+def oracle_leg(w, budget_s, gpu_results, steps, label=None):
     """cpu_baseline: the FP64 oracle unchanged, on the host cores, on a
-    bounded sample of the workload (its first patches / first steps within
-    ``budget_s``).  Then parity: each GPU result in ``gpu_results``
+    bounded sample of the workload: rounds of one step of every patch, the
+    first ones, until ``budget_s`` has passed (at most 1000 rounds).  Then
+    parity: each GPU result in ``gpu_results``
     ({label: (precision, E, B) per patch as float64 host arrays}) against the
     oracle.  Vacuum: K steps against one oracle step of K dt per patch (the
     exact per-mode flow; the oracle's semigroup pins cover the identity).
@@ -284,29 +309,26 @@ def oracle_leg(w, budget_s, gpu_results, steps):
 
     workers = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cells = 0
-    nsteps = 0
+    rounds = 0
+    state = [([np.asarray(a, np.float32).astype(np.float64) for a in w.E0[pi]],
+              [np.asarray(a, np.float32).astype(np.float64) for a in w.B0[pi]])
+             for pi in range(len(w.patches))]
     t0 = time.perf_counter()
-    for pi, p in enumerate(w.patches):
-        E = [np.asarray(a, np.float32).astype(np.float64) for a in w.E0[pi]]
-        B = [np.asarray(a, np.float32).astype(np.float64) for a in w.B0[pi]]
-        n = 0
-        while True:
+    while time.perf_counter() - t0 < budget_s and rounds < 1000:
+        for pi, p in enumerate(w.patches):
             J = ro = rn = None
             if w.sources:
-                J, ro, rn = w.schedule[pi].sources(n, dtype=np.float32)
+                J, ro, rn = w.schedule[pi].sources(rounds, dtype=np.float32)
                 J = [np.asarray(a, np.float64) for a in J]
                 ro, rn = np.asarray(ro, np.float64), np.asarray(rn, np.float64)
-            E, B = oracle.psatd_step(E, B, J, ro, rn, d=p.d, dt=p.dt, workers=workers)
-            n += 1
+            state[pi] = oracle.psatd_step(*state[pi], J, ro, rn, d=p.d, dt=p.dt, workers=workers)
             cells += p.cells
-            if time.perf_counter() - t0 > budget_s or n >= 1000 or len(w.patches) > 1:
-                break
-        nsteps = max(nsteps, n)
-        if time.perf_counter() - t0 > budget_s:
-            break
+        rounds += 1
     el = time.perf_counter() - t0
-    sample = (f"{w.name}: first {nsteps} step(s) of its single grid" if len(w.patches) == 1 else
-              f"{w.name}: 1 step of each of the first {pi + 1} patches")
+    del state
+    label = label or w.name
+    sample = (f"{label}: first {rounds} step(s) of its single grid" if len(w.patches) == 1 else
+              f"{label}: first {rounds} step(s) of each of its {len(w.patches)} patches")
     cpu = {"value": cells / el, "unit": "cell-steps/s", "cores": workers, "kind": "oracle",
            "sample": sample + f", {el:.1f} s, scipy.fft FP64 + numpy update"}
 
@@ -377,6 +399,8 @@ def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
     order, with the relative difference of the two after the timed steps."""
     import torch
 
+    import fixtures
+
     steps = args.steps or 100
     w = build_inputs(args.workload, steps)
     p = w.patches[0]
@@ -406,6 +430,21 @@ def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
     torch.cuda.synchronize()
     sec_dom = time.perf_counter() - t0
     sec_glob = time_steps(plan, E, B, J, ro, rn, steps, min(args.warmup, 5), not w.sources)
+    # the same local patches as an ordinary batched plan (no guard exchange):
+    # what the local grids cost by themselves, so that the exchange's own cost
+    # is the difference
+    lp = fixtures.Patch(p.ndim, local[0], local[1], local[2], p.dx, p.dy, p.dz, p.dt)
+    lplan = pk.Plan([lp] * npatch, precision="fp32", source_mode=mode, path="fused", order=order,
+                    centered_stencil=True, graph=True, autotune=True)
+    n = lplan.total_elements
+    LE = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    LB = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(3)]
+    LJ = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(3)] if w.sources else None
+    Lro = torch.zeros(n, dtype=torch.float32, device="cuda") if w.sources else None
+    Lrn = torch.zeros(n, dtype=torch.float32, device="cuda") if w.sources else None
+    sec_loc = time_steps(lplan, LE, LB, LJ, Lro, Lrn, steps, min(args.warmup, 5), not w.sources)
+    lplan.close()
+    del LE, LB, LJ, Lro, Lrn
     diff = float(np.sqrt(sum(float(torch.sum((a.double() - b.double()) ** 2)) for a, b in zip(E + B, E2 + B2))
                          / sum(float(torch.sum(b.double() ** 2)) for b in E + B)))
     out = {"metric": "PSATD guard-cell decomposition cell-steps/s (global interior cells), 1 GPU",
@@ -415,6 +454,8 @@ def bench_decomposition(pk, args, parts=(2, 1, 2), guard=128, order=16):
                       "stencil": "centered", "patches": npatch, "local_shape": list(local),
                       "storage": "f32"},
            "undecomposed": {"value": w.cells * steps / sec_glob, "ms_per_step": 1e3 * sec_glob / steps},
+           "local_patches_alone": {"ms_per_step": 1e3 * sec_loc / steps,
+                                   "note": "the same local patches as a batched plan, no guard exchange"},
            "rel_l2_vs_undecomposed": diff}
     dom.close()
     plan.close()
@@ -597,7 +638,7 @@ def bench_large_3d(pk, args, steps):
     torch.cuda.synchronize()
     cells = p.cells
     log(f"[bench]   {fixtures.CONFIG_NAMES[4]}: {cells} cells, {time.time() - t:.1f} s")
-    plan = pk.Plan([p], precision="fp32", source_mode="rho", path="fused", graph=True, autotune=True)
+    plan = fp32_plan(pk, args, [p], "rho")
     log("[bench] fp32 fused plan:\n" + plan.info)
     log(f"[bench] timing {steps} fp32 steps (+{args.warmup} warmup) ...")
     sec = time_steps(plan, E, B, J, ro, rn, steps, args.warmup, False)
@@ -638,10 +679,12 @@ def bench_large_3d(pk, args, steps):
                                                              host_fields(pl, Bs, ws.patches))
             pl.close()
         log(f"[bench] oracle on host cores (~{args.cpu_budget:.0f} s budget), 64^3 same-seed run ...")
-        cpu, parity = oracle_leg(ws, args.cpu_budget, res, 1)
+        cpu, parity = oracle_leg(ws, args.cpu_budget, res, 1,
+                                 label=f"{fixtures.CONFIG_NAMES[4]} recipe and seed on a 64x64x64 grid")
     cfg = {"workload": fixtures.CONFIG_NAMES[4], "cells": cells, "patches": 1,
            "steps_per_config": 100, "source_form": "rho", "storage": "f32", "arithmetic": "f64",
-           "path": "fused", "graph": True, "autotune": True, "inputs": "built on the GPU"}
+           "path": "fused", "graph": True,
+           "autotune": "saved choices" if args.tuning_in else True, "inputs": "built on the GPU"}
     out = result_line(fixtures.CONFIG_NAMES[4], cells, steps, args, ms_step, value, cfg, dom_name,
                       achieved, step_bytes, passes, fp64, parity, cpu)
     print(json.dumps(out), flush=True)
@@ -652,7 +695,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=None,
+                    help="workload index (default: 3, the batched patches; 1, the 4096 x 4096 grid, "
+                         "for --decomposition and --contrast)")
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -660,6 +705,11 @@ def main():
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--tuning-out", metavar="PATH",
+                    help="save the timed plan's kernel choices (psatd_plan_tuning) to PATH")
+    ap.add_argument("--tuning-in", metavar="PATH",
+                    help="build the timed plan from kernel choices saved by --tuning-out "
+                         "instead of autotuning it")
     ap.add_argument("--decomposition", action="store_true",
                     help="instead of the default line: time the guard-cell domain decomposition "
                          "(2 x 2 boxes, 128 guard cells, centered order 16) on the same workload")
@@ -671,6 +721,11 @@ def main():
                          "files (FETCH_SIZE, WRITE_SIZE) of this script, scaled by its "
                          "calibration copy (--copy-calibration-mib, default 1024)")
     args = ap.parse_args()
+    if args.workload is None:
+        args.workload = 1 if (args.decomposition or args.contrast) else 3
+    if (args.decomposition or args.contrast) and args.workload not in (0, 1, 2):
+        print("--decomposition and --contrast take a single-grid workload (0, 1 or 2)", file=sys.stderr)
+        sys.exit(2)
     if args.ingest_traffic:
         data = ingest_traffic(*args.ingest_traffic, args.workload, args.copy_calibration_mib or 1024)
         print(json.dumps(data, indent=1, sort_keys=True))
@@ -709,8 +764,7 @@ def main():
     cells = w.cells
 
     # ------------------------------------------------ FP32 storage, fused path
-    plan = pk.Plan(w.patches, precision="fp32", source_mode=mode, path="fused", graph=True,
-                   autotune=True)
+    plan = fp32_plan(pk, args, w.patches, mode)
     log("[bench] fp32 fused plan:\n" + plan.info)
     E, B, J, ro, rn = device_fields(w, plan, np.float32)
     # parity run of the timed configuration (the oracle leg checks it): the
@@ -758,7 +812,8 @@ def main():
     ws_bytes = sum(p.cells * 4 * nin * (3 if p.ndim == 3 else 2) for p in w.patches)
     cfg = {"workload": w.name, "cells": cells, "patches": len(w.patches),
            "steps_per_config": default_steps, "source_form": mode, "storage": "f32",
-           "arithmetic": "f64", "path": "fused", "graph": True, "autotune": True,
+           "arithmetic": "f64", "path": "fused", "graph": True,
+           "autotune": "saved choices" if args.tuning_in else True,
            "working_set_bytes": ws_bytes}
     out = result_line(w.name, cells, steps, args, ms_step, value, cfg, dom_name, achieved,
                       step_bytes, passes, fp64, parity, cpu, sources)

@@ -148,6 +148,29 @@ typedef struct {
 psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches,
                         int32_t npatches, int32_t device, psatd_plan_t* out);
 
+/* The plan's kernel choices as a NUL-terminated string: per pass, the
+ * kernel family, tile (lines per workgroup), modes or points per thread and
+ * launch grid that psatd_plan chose (by PSATD_FLAG_AUTOTUNE's timing, or its
+ * defaults).  *needed (if not NULL) receives the string's size including the
+ * NUL; buf may be NULL to query it, else PSATD_ERR_INVALID_ARG if len is
+ * smaller.  The string is meant for psatd_plan_tuned on the same
+ * configuration and patches: autotuning once and reusing its result skips
+ * the timing launches at plan time, and keeps the kernel choice fixed where
+ * timing would be distorted (under a profiler that serializes dispatches). */
+psatd_status psatd_plan_tuning(psatd_plan_t plan, char* buf, size_t len, size_t* needed);
+
+/* psatd_plan with the kernel choices of `tuning` (a string from
+ * psatd_plan_tuning) instead of its defaults or autotuning: no timing launch
+ * (PSATD_FLAG_AUTOTUNE is ignored).  Each choice is checked against the
+ * candidates the autotuner would offer this plan (the same kernels, tiles and
+ * grids); PSATD_ERR_INVALID_ARG if the string does not parse, has a choice
+ * count other than the plan's pass count, or names a choice the plan does
+ * not offer.  Results are those of the plan the string came from, bit for
+ * bit.  Other errors as psatd_plan. */
+psatd_status psatd_plan_tuned(const psatd_config* cfg, const psatd_patch_desc* patches,
+                              int32_t npatches, int32_t device, const char* tuning,
+                              psatd_plan_t* out);
+
 /* Host-only planning: the same validation, workspace layout, pass and
  * work-list construction and work-list verification as psatd_plan, with no
  * HIP call and no device memory (the autotune and graph flags are ignored:

@@ -39,7 +39,7 @@ EXPORTED_SYMBOLS = (
     "psatd_plan_info", "psatd_destroy", "psatd_status_string", "psatd_last_error",
     "psatd_domain_create", "psatd_domain_local_shape", "psatd_domain_push", "psatd_domain_destroy",
     "psatd_fdtd_plan", "psatd_fdtd_push", "psatd_fdtd_destroy", "psatd_push_scratch",
-    "psatd_plan_describe",
+    "psatd_plan_describe", "psatd_plan_tuning", "psatd_plan_tuned",
 )
 SCRATCH_BYTES = 256 << 20  # PSATD_SCRATCH_BYTES
 
@@ -89,12 +89,19 @@ def load_library(path: Optional[str] = None):
         raise RuntimeError(
             f"{p} not found: the HIP library is not built (run `python -m "
             "paper_1608_05739_amd.build` or __graft_entry__.build()); there is no fallback")
+    # torch ships its own HIP runtime.  Loading it before the library keeps
+    # the process on the runtime torch uses: with the library's runtime loaded
+    # and initialized first, torch's later initialization finds no GPU.
+    import torch  # noqa: F401  (loaded for its HIP runtime; no device is touched)
     lib = ctypes.CDLL(p)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     lib.psatd_plan.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(PatchDesc), i32, i32,
                                ctypes.POINTER(vp)]
     lib.psatd_plan_describe.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(PatchDesc), i32,
                                         ctypes.POINTER(sz), ctypes.c_char_p, sz]
+    lib.psatd_plan_tuned.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(PatchDesc), i32, i32,
+                                     ctypes.c_char_p, ctypes.POINTER(vp)]
+    lib.psatd_plan_tuning.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
     lib.psatd_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.psatd_set_workspace.argtypes = [vp, vp, sz]
     lib.psatd_push.argtypes = [vp, ctypes.POINTER(Fields), i32, vp]
@@ -262,12 +269,15 @@ class Plan:
     ``pstd=True`` runs the PSTD contrast solver instead (leapfrog: B holds B
     at half-integer times; source_mode "vacuum" or "j").  ``radix4_lines=True``
     runs the generic line passes as radix-4 stages at 4 points per thread.
+    ``tuning`` (a string from :attr:`tuning` of a plan with the same
+    arguments) applies that plan's kernel choices instead of autotuning
+    (``psatd_plan_tuned``).
     """
 
     def __init__(self, patches: Sequence, *, precision="fp32", source_mode="vacuum",
                  path="fused", order=0, c=1.0, eps0=1.0, autotune=False, graph=False,
                  device=0, allocate_workspace=True, generic_kernels=False,
-                 centered_stencil=False, pstd=False, radix4_lines=False):
+                 centered_stencil=False, pstd=False, radix4_lines=False, tuning=None):
         self._lib = load_library()
         self._plan = None
         ps, descs, self.offsets, self.total_elements = _patch_descs(patches)
@@ -280,11 +290,25 @@ class Plan:
                           generic_kernels=generic_kernels, centered_stencil=centered_stencil,
                           pstd=pstd, radix4_lines=radix4_lines)
         handle = ctypes.c_void_p()
-        _check(self._lib, self._lib.psatd_plan(ctypes.byref(cfg), descs, len(ps), int(device),
-                                                ctypes.byref(handle)))
+        if tuning is None:
+            _check(self._lib, self._lib.psatd_plan(ctypes.byref(cfg), descs, len(ps), int(device),
+                                                    ctypes.byref(handle)))
+        else:
+            _check(self._lib, self._lib.psatd_plan_tuned(ctypes.byref(cfg), descs, len(ps),
+                                                          int(device), tuning.encode(),
+                                                          ctypes.byref(handle)))
         self._plan = handle
 
     # -------------------------------------------------------------- queries
+    @property
+    def tuning(self) -> str:
+        """The plan's kernel choices (``psatd_plan_tuning``), for ``Plan(..., tuning=)``."""
+        n = ctypes.c_size_t()
+        _check(self._lib, self._lib.psatd_plan_tuning(self._plan, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self._lib, self._lib.psatd_plan_tuning(self._plan, buf, n.value, None))
+        return buf.value.decode()
+
     @property
     def workspace_size(self) -> int:
         n = ctypes.c_size_t()

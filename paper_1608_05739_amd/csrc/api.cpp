@@ -164,11 +164,20 @@ struct Pass {
   int mpt = 0;             // fused pass: modes per thread
   int ppt = 0;             // line passes: points per thread per FFT stage
   double tuned_ms = -1.0;  // mean launch time at the chosen grid (autotune), else -1
+  int grid_choice = -1;    // the grid code given to set_grid by tuning, -1: the default grid
+  bool tuning_applied = false;  // chosen by a tuning string (psatd_plan_tuned)
   std::vector<int> comps;  // line passes: the components they transform
   int lines = 0;           // line passes: lines per workgroup (the tile)
   int region = 0;          // wave-resident passes: double2 elements of LDS per wavefront
   bool ct = false;         // line passes: the compile-time-length kernels (ct_line_kernel),
   std::vector<SubLaunch> subs;  // ct line and wave x passes: one launch per length
+};
+
+// One pass's choice in a tuning string: pass type, compile-time flag, lines
+// per workgroup, modes per thread, points per thread, grid (-1: the plan's
+// default grid).
+struct Choice {
+  int type, ct, lines, mpt, ppt, grid;
 };
 
 const char* line_pass_name(int kind) {
@@ -195,6 +204,7 @@ struct psatd_plan_s {
   int src_form = 0; // SourceForm run by the generic kernels (PSATD forms or PSTD)
   size_t elem = 4;  // sizeof storage scalar
   std::vector<psatd_patch_desc> desc;
+  std::vector<Choice> tuning;  // kernel choices to apply instead of autotuning (psatd_plan_tuned)
   std::vector<PatchDev> host_patches;
   PatchDev* d_patches = nullptr;
   void* d_tables = nullptr;
@@ -1160,6 +1170,153 @@ psatd_status build_graph(psatd_plan_s* plan) {
   return PSATD_OK;
 }
 
+// ---------------------------------------------------------------- tuning
+// The candidates of one pass: the plan's own choice first, then other tiles
+// (lines per workgroup), modes or points per thread, radix schedules and
+// kernel families.  Each keeps its host work list, checked against the plan
+// by verify_pass; it is uploaded only when timed or chosen.
+struct Cand {
+  Pass pass;
+  std::vector<WorkItem> its;  // empty for the plan's own choice (already on the device)
+};
+
+std::vector<Cand> pass_candidates(const psatd_plan_s* plan, const Pass& ps) {
+  std::vector<Cand> cands;
+  cands.push_back(Cand{ps, {}});
+  // (fused passes: also at every compiled modes-per-thread choice that holds
+  // the z lines; these run the same arithmetic per line)
+  // (line passes: also at both radix schedules, radix-4 stages at 4 points
+  // per thread and radices up to 8 at 8; they round differently, and each
+  // is checked against the oracle by the tests)
+  // (the wave-resident z pass: also the generic fused pass, at every choice)
+  // (line passes: also the compile-time and the wave-resident kernels where
+  // they apply)
+  const bool linelike = ps.type == kLine || ps.type == kWaveX;
+  std::vector<int> vars = {0};
+  if (ps.type == kFused || ps.type == kWaveZ) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
+  if (linelike) vars = {4, kMaxPts};
+  auto add = [&](Pass c, std::vector<WorkItem>& its) {
+    for (const Cand& x : cands)
+      if (x.pass.type == c.type && x.pass.ct == c.ct && x.pass.lines == c.lines &&
+          x.pass.mpt == c.mpt && x.pass.ppt == c.ppt)
+        return;
+    c.d_items = nullptr;
+    if (verify_pass(plan, c, its.data()) != PSATD_OK) return;
+    cands.push_back(Cand{c, std::move(its)});
+  };
+  if (linelike && !(ps.type == kLine && ps.ct) && ct_line_eligible(ps.line_kind, plan)) {
+    std::vector<WorkItem> its;
+    add(make_ct_line_pass(ps.line_kind, plan, ps.comps, its), its);
+  }
+  if (linelike && ps.type != kWaveX && wave_line_eligible(ps.line_kind, plan)) {
+    std::vector<WorkItem> its;
+    add(make_wave_x_pass(ps.line_kind, plan, ps.comps, its), its);
+  }
+  if (linelike || ps.type == kFused || ps.type == kWaveZ) {
+    for (int m : vars) {
+      for (int R : {1, 2, 4, 8, 16, 32}) {
+        std::vector<WorkItem> its;
+        Pass c;
+        if (linelike) {
+          c = make_line_pass(ps.line_kind, plan, ps.comps, its, R, m);
+        } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
+          continue;
+        }
+        add(c, its);
+      }
+    }
+  }
+  return cands;
+}
+
+// The launch grids a candidate is timed at: one workgroup per item (the wave
+// z pass: one wavefront per item), or a persistent grid of k workgroups per
+// CU; per-length launches take a code (0: every item its own workgroup, k: k
+// per CU) that set_grid turns into each launch's grid.
+std::vector<int> grid_choices(const psatd_plan_s* plan, const Pass& c) {
+  if (!c.subs.empty()) return {0, 1, 2, 4, 8};
+  const int full = c.type == kWaveZ ? c.shape.grid : c.nitems;
+  std::vector<int> grids = {full};
+  for (int k : {1, 2, 4, 8})
+    if (k * plan->num_cus < full) grids.push_back(k * plan->num_cus);
+  return grids;
+}
+
+bool parse_tuning(const char* text, std::vector<Choice>* out) {
+  out->clear();
+  const char* p = text;
+  if (std::strncmp(p, "psatd-tuning-1", 14) != 0) return false;
+  p += 14;
+  while (*p == ';') {
+    ++p;
+    Choice c{};
+    int used = 0;
+    if (std::sscanf(p, "%d,%d,%d,%d,%d,%d%n", &c.type, &c.ct, &c.lines, &c.mpt, &c.ppt, &c.grid,
+                    &used) != 6)
+      return false;
+    out->push_back(c);
+    p += used;
+  }
+  return *p == '\0' && !out->empty();
+}
+
+// Upload a candidate's work list into plan-owned device memory.
+psatd_status upload_items(psatd_plan_s* plan, Cand& c, WorkItem** d) {
+  *d = nullptr;
+  if (c.its.empty()) return PSATD_OK;
+  hipError_t e = hipMalloc(d, sizeof(WorkItem) * c.its.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(*d, c.its.data(), sizeof(WorkItem) * c.its.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (*d) (void)hipFree(*d);
+    *d = nullptr;
+    return hip_fail(e, "tuning: work list upload");
+  }
+  c.pass.d_items = *d;
+  return PSATD_OK;
+}
+
+// Apply the choices of a tuning string (from psatd_plan_tuning of a plan with
+// the same configuration and patches): no timing launch.
+psatd_status apply_tuning(psatd_plan_s* plan, const std::vector<Choice>& choice) {
+  if (choice.size() != plan->passes.size())
+    return fail(PSATD_ERR_INVALID_ARG, "tuning: " + std::to_string(choice.size()) +
+                                           " choices for a plan of " +
+                                           std::to_string(plan->passes.size()) + " passes");
+  for (size_t i = 0; i < plan->passes.size(); ++i) {
+    Pass& ps = plan->passes[i];
+    const Choice& ch = choice[i];
+    std::vector<Cand> cands = pass_candidates(plan, ps);
+    int pick = -1;
+    for (size_t ci = 0; ci < cands.size() && pick < 0; ++ci) {
+      const Pass& c = cands[ci].pass;
+      if (c.type == ch.type && static_cast<int>(c.ct) == ch.ct && c.lines == ch.lines &&
+          c.mpt == ch.mpt && c.ppt == ch.ppt)
+        pick = static_cast<int>(ci);
+    }
+    if (pick < 0)
+      return fail(PSATD_ERR_INVALID_ARG,
+                  std::string("tuning: no such kernel choice for pass ") + ps.name);
+    Cand& c = cands[pick];
+    if (ch.grid >= 0) {
+      const std::vector<int> grids = grid_choices(plan, c.pass);
+      if (std::find(grids.begin(), grids.end(), ch.grid) == grids.end())
+        return fail(PSATD_ERR_INVALID_ARG, std::string("tuning: grid not offered for pass ") + ps.name);
+    }
+    if (!plan->dry) {
+      WorkItem* d = nullptr;
+      psatd_status st = upload_items(plan, c, &d);
+      if (st != PSATD_OK) return st;
+      if (d) plan->extra_items.push_back(d);
+    }
+    ps = c.pass;
+    if (ch.grid >= 0) set_grid(plan, ps, ch.grid);
+    ps.grid_choice = ch.grid;
+    ps.tuning_applied = true;
+  }
+  return PSATD_OK;
+}
+
 // Launch-shape autotuning (PSATD_FLAG_AUTOTUNE).  Every kernel loops over its
 // work list, so any grid size is correct; what changes is whether one
 // workgroup per CU walks the list (and prefetches its next item) or the
@@ -1227,96 +1384,15 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
     return e == hipSuccess ? ms / kReps : -1.0;
   };
   for (Pass& ps : plan->passes) {
-    // Candidate tiles: line passes are rebuilt with other lines-per-workgroup
-    // counts (each work list checked on the host, then uploaded); every tile
-    // is timed at each candidate grid.
-    struct Cand {
-      Pass pass;
-      WorkItem* d = nullptr;  // owned device work list (nullptr: the plan's)
-    };
-    std::vector<Cand> cands;
-    cands.push_back(Cand{ps, nullptr});
-    // (fused passes: also at every compiled modes-per-thread choice that holds
-    // the z lines; these run the same arithmetic per line)
-    // (line passes: also at both radix schedules, radix-4 stages at 4 points
-    // per thread and radices up to 8 at 8; they round differently, and each
-    // is checked against the oracle by the tests)
-    // (the wave-resident z pass: also the generic fused pass, at every choice)
-    // (line passes: also the compile-time and the wave-resident kernels where
-    // they apply)
-    const bool linelike = ps.type == kLine || ps.type == kWaveX;
-    std::vector<int> vars = {0};
-    if (ps.type == kFused || ps.type == kWaveZ) vars = fused_mpt_choices(plan->cfg.precision, plan->ndim);
-    if (linelike) vars = {4, kMaxPts};
-    // a checked and uploaded candidate work list
-    auto add_cand = [&](Pass c, const std::vector<WorkItem>& its) {
-      if (verify_pass(plan, c, its.data()) != PSATD_OK) return;
-      WorkItem* d = nullptr;
-      e = hipMalloc(&d, sizeof(WorkItem) * its.size());
-      if (e == hipSuccess)
-        e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
-      if (e == hipSuccess) {
-        c.d_items = d;
-        cands.push_back(Cand{c, d});
-      } else if (d) {
-        (void)hipFree(d);
-      }
-    };
-    if (linelike && !(ps.type == kLine && ps.ct) && ct_line_eligible(ps.line_kind, plan)) {
-      std::vector<WorkItem> its;
-      add_cand(make_ct_line_pass(ps.line_kind, plan, ps.comps, its), its);
-    }
-    if (linelike && ps.type != kWaveX && wave_line_eligible(ps.line_kind, plan) &&
-        e == hipSuccess) {
-      std::vector<WorkItem> its;
-      add_cand(make_wave_x_pass(ps.line_kind, plan, ps.comps, its), its);
-    }
-    if (linelike || ps.type == kFused || ps.type == kWaveZ) {
-      for (int m : vars) {
-        if (e != hipSuccess) break;
-        for (int R : {1, 2, 4, 8, 16, 32}) {
-          std::vector<WorkItem> its;
-          Pass c;
-          if (linelike) {
-            c = make_line_pass(ps.line_kind, plan, ps.comps, its, R, m);
-          } else if (make_fused_pass(plan, its, &c, R, m) != PSATD_OK) {
-            continue;
-          }
-          bool seen = false;
-          for (const Cand& x : cands)
-            seen = seen || (x.pass.type == c.type && x.pass.ct == c.ct && x.pass.lines == c.lines &&
-                            x.pass.mpt == c.mpt && x.pass.ppt == c.ppt);
-          if (seen) continue;
-          c.d_items = nullptr;
-          if (verify_pass(plan, c, its.data()) != PSATD_OK) continue;
-          WorkItem* d = nullptr;
-          e = hipMalloc(&d, sizeof(WorkItem) * its.size());
-          if (e == hipSuccess)
-            e = hipMemcpy(d, its.data(), sizeof(WorkItem) * its.size(), hipMemcpyHostToDevice);
-          if (e != hipSuccess) {
-            if (d) (void)hipFree(d);
-            break;
-          }
-          c.d_items = d;
-          cands.push_back(Cand{c, d});
-        }
-      }
-    }
+    std::vector<Cand> cands = pass_candidates(plan, ps);
+    std::vector<WorkItem*> dev(cands.size(), nullptr);
     int best_c = 0, best_g = ps.shape.grid;
     double best_ms = 1e300;
     for (size_t ci = 0; ci < cands.size() && st == PSATD_OK && e == hipSuccess; ++ci) {
+      st = upload_items(plan, cands[ci], &dev[ci]);
+      if (st != PSATD_OK) break;
       Pass& c = cands[ci].pass;
-      // one workgroup per item (the wave pass: one wavefront per item), or a
-      // persistent grid of k workgroups per CU
-      const int full = c.type == kWaveZ ? c.shape.grid : c.nitems;
-      std::vector<int> grids = {full};
-      if (!c.subs.empty()) {
-        grids = {0, 1, 2, 4, 8};  // per length launch: every item its own, or k per CU
-      } else {
-        for (int k : {1, 2, 4, 8})
-          if (k * plan->num_cus < full) grids.push_back(k * plan->num_cus);
-      }
-      for (int g : grids) {
+      for (int g : grid_choices(plan, c)) {
         set_grid(plan, c, g);
         const double ms = time_pass(c);
         if (ms < 0.0) break;
@@ -1327,15 +1403,16 @@ psatd_status autotune_passes(psatd_plan_s* plan) {
         }
       }
     }
-    for (size_t ci = 1; ci < cands.size(); ++ci)
-      if (static_cast<int>(ci) != best_c || st != PSATD_OK || e != hipSuccess)
-        (void)hipFree(cands[ci].d);
+    for (size_t ci = 0; ci < cands.size(); ++ci)
+      if (dev[ci] && (static_cast<int>(ci) != best_c || st != PSATD_OK || e != hipSuccess))
+        (void)hipFree(dev[ci]);
     if (st != PSATD_OK || e != hipSuccess) break;
     if (best_c != 0) {
       ps = cands[best_c].pass;
-      plan->extra_items.push_back(cands[best_c].d);
+      plan->extra_items.push_back(dev[best_c]);
     }
     set_grid(plan, ps, best_g);
+    ps.grid_choice = best_g;
     ps.tuned_ms = best_ms;
   }
   cleanup();
@@ -1557,7 +1634,10 @@ psatd_status build_plan(psatd_plan_s* plan) {
     }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "plan tables");
-    if (cfg.flags & PSATD_FLAG_AUTOTUNE) {
+    if (!plan->tuning.empty()) {
+      psatd_status st = apply_tuning(plan, plan->tuning);
+      if (st != PSATD_OK) return st;
+    } else if (cfg.flags & PSATD_FLAG_AUTOTUNE) {
       psatd_status st = autotune_passes(plan);
       if (st != PSATD_OK) return st;
     }
@@ -1583,18 +1663,22 @@ psatd_status build_plan(psatd_plan_s* plan) {
                   (ps.type == kWaveZ || ps.type == kWaveX)
                       ? "wave"
                       : (ps.ct ? "compile-time" : (ps.type >= kFastXFwd ? "4096" : "generic")),
-                  ps.tuned_ms >= 0.0 ? " (autotuned)" : "");
+                  ps.tuning_applied ? " (tuning applied)" : (ps.tuned_ms >= 0.0 ? " (autotuned)" : ""));
     plan->info += buf;
   }
   return PSATD_OK;
 }
 
 psatd_status create_plan(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t npatches,
-                         int32_t device, const GlobalMap* maps, psatd_plan_t* out) {
+                         int32_t device, const GlobalMap* maps, psatd_plan_t* out,
+                         const char* tuning = nullptr) {
   try {
     if (!out) return fail(PSATD_ERR_INVALID_ARG, "out is NULL");
     psatd_status st = validate(cfg, patches, npatches);
     if (st != PSATD_OK) return st;
+    std::vector<Choice> choices;
+    if (tuning && !parse_tuning(tuning, &choices))
+      return fail(PSATD_ERR_INVALID_ARG, "tuning string does not parse");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
       return fail(PSATD_ERR_HIP, "no HIP device available");
@@ -1631,6 +1715,7 @@ psatd_status create_plan(const psatd_config* cfg, const psatd_patch_desc* patche
     }
     plan->desc.assign(patches, patches + npatches);
     if (maps) plan->maps.assign(maps, maps + npatches);
+    plan->tuning = choices;
     st = build_plan(plan);
     if (st != PSATD_OK) {
       free_plan_memory(plan);
@@ -1664,6 +1749,30 @@ extern "C" {
 psatd_status psatd_plan(const psatd_config* cfg, const psatd_patch_desc* patches, int32_t npatches,
                         int32_t device, psatd_plan_t* out) {
   return create_plan(cfg, patches, npatches, device, nullptr, out);
+}
+
+psatd_status psatd_plan_tuned(const psatd_config* cfg, const psatd_patch_desc* patches,
+                              int32_t npatches, int32_t device, const char* tuning,
+                              psatd_plan_t* out) {
+  if (!tuning) return fail(PSATD_ERR_INVALID_ARG, "tuning is NULL");
+  return create_plan(cfg, patches, npatches, device, nullptr, out, tuning);
+}
+
+psatd_status psatd_plan_tuning(psatd_plan_t plan, char* buf, size_t len, size_t* needed) {
+  if (!plan) return fail(PSATD_ERR_INVALID_ARG, "plan is NULL");
+  std::string t = "psatd-tuning-1";
+  char tok[96];
+  for (const Pass& ps : plan->passes) {
+    std::snprintf(tok, sizeof(tok), ";%d,%d,%d,%d,%d,%d", static_cast<int>(ps.type),
+                  ps.ct ? 1 : 0, ps.lines, ps.mpt, ps.ppt, ps.grid_choice);
+    t += tok;
+  }
+  if (needed) *needed = t.size() + 1;
+  if (buf) {
+    if (len < t.size() + 1) return fail(PSATD_ERR_INVALID_ARG, "tuning buffer too small");
+    std::memcpy(buf, t.c_str(), t.size() + 1);
+  }
+  return PSATD_OK;
 }
 
 psatd_status psatd_plan_describe(const psatd_config* cfg, const psatd_patch_desc* patches,

@@ -224,6 +224,24 @@ int main() {
   for (int s = -8; s <= 1; ++s) expect(psatd_status_string(static_cast<psatd_status>(s)) != nullptr,
                                        "status string " + std::to_string(s));
 
+  // ---- tuning strings are parsed before any device is touched
+  {
+    const auto c = config(PSATD_FP32, PSATD_VACUUM, PSATD_PATH_FUSED, 0, 0u);
+    const psatd_patch_desc p1 = patch(2, 64, 1, 96, 0.5, 0);
+    const std::string longest(100000, '9');
+    const char* bad[] = {"", "psatd-tuning-1", "psatd-tuning-1;", "psatd-tuning-1;1,2,3",
+                         "psatd-tuning-1;1,0,8,0,8,-1;", "psatd-tuning-1;1,0,8,0,8,-1x",
+                         "psatd-tuning-0;1,0,8,0,8,-1", longest.c_str()};
+    for (const char* t : bad) {
+      psatd_plan_t out = nullptr;
+      expect(psatd_plan_tuned(&c, &p1, 1, 0, t, &out) == PSATD_ERR_INVALID_ARG && out == nullptr,
+             std::string("malformed tuning \"") + std::string(t).substr(0, 40) + "\"");
+    }
+    psatd_plan_t out = nullptr;
+    expect(psatd_plan_tuned(&c, &p1, 1, 0, nullptr, &out) == PSATD_ERR_INVALID_ARG, "NULL tuning");
+    size_t n = 0;
+    expect(psatd_plan_tuning(nullptr, nullptr, 0, &n) == PSATD_ERR_INVALID_ARG, "tuning of NULL plan");
+  }
   std::printf("%d cases, %d failed\n", g_cases, g_fail);
   return g_fail == 0 ? 0 : 1;
 }

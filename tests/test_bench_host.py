@@ -99,6 +99,7 @@ def test_kernel_names_map_to_passes():
     assert bench.pass_of_kernel("void psatd::wave2d::(anonymous namespace)::wave_x_kernel<0, 128>("
                                 "psatd::PatchDev const*)") == "x_r2c_fwd"
     assert bench.pass_of_kernel("void psatd::wave2d::wave_z_fused_kernel<0>(...)") == "z_fused"
+    assert bench.pass_of_kernel("void psatd::wave2d::(anonymous namespace)::wave_z3_fused_kernel<1>(...)") == "z_fused"
     assert bench.pass_of_kernel("__amd_rocclr_copyBuffer") is None
 
 

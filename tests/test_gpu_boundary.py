@@ -230,3 +230,27 @@ def test_plans_work_after_an_out_of_memory_plan():
     plan.push(E, B, steps=2)
     torch.cuda.synchronize()
     plan.close()
+
+
+def test_plan_created_before_torch_touches_the_gpu():
+    # A fresh process whose first GPU call is the library's: torch must still
+    # find the GPU afterwards (one HIP runtime in the process), and the plan
+    # must run on torch's tensors.
+    import subprocess
+    import sys
+    say("boundary: plan before torch's first GPU call (subprocess)")
+    code = (
+        "import paper_1608_05739_amd as pk\n"
+        "plan = pk.Plan([pk.Patch(2, (16, 1, 8), (0.1, 0.1, 0.1), 0.05)])\n"
+        "import torch\n"
+        "E = [torch.zeros(plan.total_elements, device='cuda:0') for _ in range(3)]\n"
+        "B = [torch.ones(plan.total_elements, device='cuda:0') for _ in range(3)]\n"
+        "plan.push(E, B, steps=2)\n"
+        "torch.cuda.synchronize()\n"
+        "assert all(bool(torch.isfinite(t).all()) for t in E + B)\n"
+        "print('ok')\n")
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=root)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]

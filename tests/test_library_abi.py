@@ -260,3 +260,28 @@ def test_describe_reports_the_same_errors_as_plan(lib):
     with pytest.raises(pk.PsatdError) as e:
         pk.describe_plan([pk.Patch(2, (64, 1, 64), (1.0, 1.0, 1.0), 0.9)], pstd=True)
     assert e.value.status == -1 and "Courant" in str(e.value)
+
+
+@pytest.mark.parametrize("tuning", [
+    b"",                                  # no version tag
+    b"psatd-tuning-1",                    # no choices
+    b"psatd-tuning-2;1,0,8,0,8,-1",       # unknown version
+    b"psatd-tuning-1;1,0,8,0,8",          # five fields
+    b"psatd-tuning-1;1,0,8,0,8,-1;",      # trailing separator
+    b"psatd-tuning-1;1,0,8,0,8,-1 junk",  # trailing text
+])
+def test_tuned_plan_rejects_malformed_tuning_on_host(lib, tuning):
+    # the string is parsed before any device is touched
+    out = ctypes.c_void_p()
+    st = lib.psatd_plan_tuned(ctypes.byref(_cfg()), ctypes.byref(_desc()), 1, 0, tuning,
+                              ctypes.byref(out))
+    assert st == -1 and "tuning" in lib.psatd_last_error().decode()
+    assert out.value is None
+
+
+def test_tuned_plan_null_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.psatd_plan_tuned(ctypes.byref(_cfg()), ctypes.byref(_desc()), 1, 0, None,
+                                ctypes.byref(out)) == -1
+    n = ctypes.c_size_t()
+    assert lib.psatd_plan_tuning(None, None, 0, ctypes.byref(n)) == -1
