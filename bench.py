@@ -84,6 +84,7 @@ def pass_of_kernel(name):
     for key, pname in (("x_fwd_kernel", "x_r2c_fwd"), ("z_fused_kernel", "z_fused"),
                        ("x_inv_kernel", "x_c2r_inv"), ("fused_z_kernel", "z_fused"),
                        ("wave_z_fused", "z_fused"), ("wave_z3_fused", "z_fused"),
+                       ("wave_z_set", "z_fused"),
                        ("update_kernel", "update")):
         if key in name:
             return pname

@@ -151,6 +151,8 @@ struct SubLaunch {
   int first = 0;  // index of its first work item within the pass's list
   int nitems = 0;
   LaunchShape shape{};
+  int full = 0;    // workgroups that give every wave its own work (0: nitems)
+  int region = 0;  // wave z pass: double2 elements of LDS per wavefront
 };
 
 struct Pass {
@@ -571,7 +573,7 @@ void set_grid(const psatd_plan_s* plan, Pass& ps, int g) {
   }
   int total = 0;
   for (SubLaunch& sub : ps.subs) {
-    const int full = sub.nitems;
+    const int full = sub.full > 0 ? sub.full : sub.nitems;
     sub.shape.grid = g == 0 ? full : std::min(full, g * plan->num_cus);
     total += sub.shape.grid;
   }
@@ -799,6 +801,19 @@ psatd_status verify_pass(const psatd_plan_s* plan, const Pass& ps, const WorkIte
       if (w.count < 1 || w.first < 0 || w.first + w.count > P.mx * P.ny ||
           w.count > wave2d::z_lines_per_item(P.nz))
         return fail(PSATD_ERR_STATE, "z_fused (wave): item out of range");
+      if (P.ndim == 2) {
+        // each item in the launch of its z length, whose LDS holds a region
+        // of that length per wavefront
+        bool in_sub = false;
+        for (const SubLaunch& sub : ps.subs)
+          in_sub = in_sub ||
+                   (i >= sub.first && i < sub.first + sub.nitems && sub.L == P.nz &&
+                    sub.region >= wave2d::z_region(P.nz) && sub.shape.block == wave2d::kBlock &&
+                    static_cast<size_t>(sub.region) * wave2d::kWavesPerBlock * sizeof(double2) <=
+                        sub.shape.lds_bytes);
+        if (!in_sub) return fail(PSATD_ERR_STATE, "z_fused (wave): item outside its length's launch");
+        continue;
+      }
       if ((P.ndim == 2 ? wave2d::z_region(P.nz) : wave2d::z3_region(P.nz)) > ps.region ||
           static_cast<size_t>(ps.region) * wave2d::kWavesPerBlock * sizeof(double2) > ps.shape.lds_bytes)
         return fail(PSATD_ERR_STATE, "z_fused (wave): LDS region too small");
@@ -946,13 +961,52 @@ bool wave_z_eligible(const psatd_plan_s* plan) {
   return true;
 }
 
-// One work item per wavefront: the z lines (kx columns) one wave holds.
+// One work item per wavefront: the z lines (kx columns) one wave holds.  In
+// 2D, one launch per z length: lengths at 8 points per lane run one set per
+// wavefront (two wavefronts per item), the others both sets.
 Pass make_wave_z_pass(const psatd_plan_s* plan, std::vector<WorkItem>& items) {
   Pass ps;
   ps.type = kWaveZ;
   ps.name = "z_fused";
   const size_t first = items.size();
   double bytes = 0.0;
+  if (plan->ndim == 2) {
+    std::set<int> lengths;
+    for (const PatchDev& P : plan->host_patches) lengths.insert(P.nz);
+    size_t lds = 0;
+    for (int L : lengths) {
+      SubLaunch sub;
+      sub.L = L;
+      sub.first = static_cast<int>(items.size() - first);
+      const int G = wave2d::z_lines_per_item(L);
+      for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
+        const PatchDev& P = plan->host_patches[pi];
+        if (P.nz != L) continue;
+        const int nlines = P.mx * P.ny;
+        for (int l = 0; l < nlines; l += G)
+          items.push_back(WorkItem{static_cast<int>(pi), l, std::min(G, nlines - l), -1});
+        const double cells = static_cast<double>(P.nx) * P.ny * P.nz;
+        bytes += (plan->nin + 6) * cells * plan->elem;
+      }
+      sub.nitems = static_cast<int>(items.size() - first) - sub.first;
+      sub.region = wave2d::z_region(L);
+      const int waves = wave2d::z_set_supported(L) ? 2 * sub.nitems : sub.nitems;
+      sub.full = (waves + wave2d::kWavesPerBlock - 1) / wave2d::kWavesPerBlock;
+      const size_t sub_lds = static_cast<size_t>(sub.region) * wave2d::kWavesPerBlock * sizeof(double2);
+      sub.shape = LaunchShape{sub.full, wave2d::kBlock, sub_lds};
+      lds = std::max(lds, sub_lds);
+      ps.region = std::max(ps.region, sub.region);
+      ps.lines = std::max(ps.lines, G);
+      ps.subs.push_back(sub);
+    }
+    ps.nitems = static_cast<int>(items.size() - first);
+    int total = 0;
+    for (const SubLaunch& sub : ps.subs) total += sub.shape.grid;
+    ps.shape = LaunchShape{total, wave2d::kBlock, lds};
+    ps.bytes = bytes;
+    ps.d_items = reinterpret_cast<WorkItem*>(first);
+    return ps;
+  }
   for (size_t pi = 0; pi < plan->host_patches.size(); ++pi) {
     const PatchDev& P = plan->host_patches[pi];
     const int G = wave2d::z_lines_per_item(P.nz);
@@ -1034,11 +1088,18 @@ psatd_status enqueue_pass(const psatd_plan_s* plan, const Pass& ps, const FieldP
       });
       break;
     case kWaveZ:
-      e = plan->ndim == 2
-              ? wave2d::launch_z_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
-                                       ps.nitems, ws, ph, ps.region)
-              : wave2d::launch_z3_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
-                                        ps.nitems, ws, ph, ps.region);
+      if (plan->ndim == 2) {
+        e = for_subs(ps, s, fork, [&](const SubLaunch& sub, hipStream_t t) {
+          return wave2d::z_set_supported(sub.L)
+                     ? wave2d::launch_z_set(plan->src_form, sub.L, sub.shape, t, plan->d_patches,
+                                            ps.d_items + sub.first, sub.nitems, ws, ph, sub.region)
+                     : wave2d::launch_z_fused(plan->src_form, sub.shape, t, plan->d_patches,
+                                              ps.d_items + sub.first, sub.nitems, ws, ph, sub.region);
+        });
+      } else {
+        e = wave2d::launch_z3_fused(plan->src_form, ps.shape, s, plan->d_patches, ps.d_items,
+                                    ps.nitems, ws, ph, ps.region);
+      }
       break;
     case kFastXFwd:
       e = fast2d::launch_x_fwd(ps.shape, s, plan->d_patches, ps.d_items, ps.nitems, f, ws);
@@ -1094,6 +1155,24 @@ psatd_status enqueue_step(const psatd_plan_s* plan, const FieldPtrs& fp, hipStre
   return PSATD_OK;
 }
 
+// The fork of each pass launched per length, on the plan's side streams and
+// events (made with the graph; no fork where there are none).
+std::vector<Fork> plan_forks(const psatd_plan_s* plan) {
+  std::vector<Fork> forks(plan->passes.size());
+  size_t need = 0;
+  for (const Pass& ps : plan->passes)
+    if (ps.subs.size() > 1) need += 1 + ps.subs.size();
+  if (need == 0 || plan->fork_events.size() < need) return forks;
+  for (size_t i = 0, k = 0; i < plan->passes.size(); ++i)
+    if (plan->passes[i].subs.size() > 1) {
+      if (plan->side_streams.size() < plan->passes[i].subs.size()) return std::vector<Fork>(plan->passes.size());
+      forks[i].side = plan->side_streams.data();
+      forks[i].ev = plan->fork_events.data() + k;
+      k += 1 + plan->passes[i].subs.size();
+    }
+  return forks;
+}
+
 // PSATD_FLAG_GRAPH: capture one step into a graph whose kernels read the
 // field pointers from the plan's device table, and instantiate it.  Runs at
 // plan time and in psatd_set_workspace (the step needs the workspace), so
@@ -1141,13 +1220,7 @@ psatd_status build_graph(psatd_plan_s* plan) {
     if (e != hipSuccess) return hip_fail(e, "fork event");
     plan->fork_events.push_back(ev);
   }
-  std::vector<Fork> forks(plan->passes.size());
-  for (size_t i = 0, k = 0; i < plan->passes.size(); ++i)
-    if (plan->passes[i].subs.size() > 1) {
-      forks[i].side = plan->side_streams.data();
-      forks[i].ev = plan->fork_events.data() + k;
-      k += 1 + plan->passes[i].subs.size();
-    }
+  const std::vector<Fork> forks = plan_forks(plan);
   FieldPtrs fp{};
   fp.table = plan->d_fieldtab;
   e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
@@ -1838,11 +1911,14 @@ static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int
     std::vector<hipEvent_t> ev(2 * np * nsteps);
     for (auto& x : ev)
       if (hipEventCreate(&x) != hipSuccess) return fail(PSATD_ERR_HIP, "hipEventCreate");
+    // a graph plan's per-length launches run as parallel branches, as in
+    // its graph, so each pass is timed as the graph runs it
+    const std::vector<Fork> forks = plan_forks(plan);
     psatd_status rs = PSATD_OK;
     for (int n = 0; n < nsteps && rs == PSATD_OK; ++n)
       for (int i = 0; i < np && rs == PSATD_OK; ++i) {
         (void)hipEventRecord(ev[2 * (n * np + i)], s);
-        rs = enqueue_pass(plan, plan->passes[i], fp, s, plan->ws);
+        rs = enqueue_pass(plan, plan->passes[i], fp, s, plan->ws, forks[i].side ? &forks[i] : nullptr);
         (void)hipEventRecord(ev[2 * (n * np + i) + 1], s);
       }
     hipError_t e = hipStreamSynchronize(s);

@@ -11,6 +11,16 @@
 // items.  The spectra keep the layout of the generic kernels ([kx][z], FP32,
 // column 0 carrying the DC and Nyquist columns packed; both have kx = 0), so
 // these passes combine with the generic x passes.
+//
+// Two kernels.  wave_z_fused_kernel (every compiled length, one launch over
+// all of them) has each wave run both sets of its lines, the second set's
+// loads in flight during the first set's inverse transforms: about 460
+// registers, one wave per SIMD, speed from the work each wave keeps in
+// flight.  wave_z_set_kernel<L> (the lengths at 8 points per lane, one launch
+// per length) gives each wave one set of its lines, so that a wave's state
+// fits 256 registers and two waves share each SIMD; the other wave hides
+// each one's LDS and memory waits.  Both compute every mode the same way, so
+// their results are identical.
 #include <hip/hip_runtime.h>
 
 #include "groups.hpp"
@@ -27,7 +37,7 @@ __device__ __forceinline__ float2 d2f(double2 v) {
 }
 
 // Per-item state of a wave: its lines, the lane's position, and the values
-// it requests once per item (twiddle bases, mode wavenumbers, kx).
+// it requests once per item (twiddle bases, kx).
 template <int L>
 struct ZItem {
   using LN = wfft::Line<L>;
@@ -43,7 +53,6 @@ struct ZItem {
   int loff;
   long long cs;
   wfft::Twiddles<L> tw;
-  double kzv[NP];
   double kx;
 
   __device__ __forceinline__ ZItem(const PatchDev* p, const WorkItem& wi, float* ws, int lane)
@@ -53,8 +62,6 @@ struct ZItem {
     loff = (active ? g : 0) * L + s;  // inactive lanes: a valid line
     cs = P->comp_stride;
     tw.load(P->fz.tw, s);
-#pragma unroll
-    for (int m = 0; m < NP; ++m) kzv[m] = gload(P->kz, s + S * m);
     kx = gload(P->kx, wi.first + (active ? g : 0));
   }
 };
@@ -63,7 +70,10 @@ struct ZItem {
 // forward transforms and the per-mode update, and the inverse transforms of
 // the outputs with their stores.  The phases are separate so that the next
 // set's loads can be issued while this set's inverse transforms run.
-template <int L, int SRC, int GR>
+// BAR: scheduling barriers between the transforms and between the modes, so
+// that the compiler does not overlap them (and hold their registers at once);
+// for the kernel that runs at two waves per SIMD.
+template <int L, int SRC, int GR, bool BAR>
 struct ZSet {
   using Gr = Group<GR, SRC>;
   static constexpr int NP = wfft::Line<L>::P;
@@ -91,11 +101,16 @@ struct ZSet {
       wfft::fft<L, -1>(v, region, it.g, it.s, it.tw);
 #pragma unroll
       for (int m = 0; m < NP; ++m) held[slot][m] = d2f(v[m]);
+      if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);
     });
     const double dt = it.P->dt;
+    // the modes' kz, requested here rather than held through the transforms
+    double kzv[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) kzv[m] = gload(it.P->kz, it.s + ZItem<L>::S * m);
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
-      const double kz = it.kzv[m];
+      const double kz = kzv[m];
       double2 E[3] = {}, B[3] = {}, J[3] = {};
       double2 ro = make_double2(0.0, 0.0), rn = make_double2(0.0, 0.0);
       static_for<0, NIN>([&](auto sc) __attribute__((always_inline)) {
@@ -122,6 +137,7 @@ struct ZSet {
         if constexpr (comp < 3) held[Gr::out_slot[o]][m] = d2f(Eo[comp]);
         else held[Gr::out_slot[o]][m] = d2f(Bo[comp - 3]);
       });
+      if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);
     }
   }
 
@@ -139,6 +155,7 @@ struct ZSet {
 #pragma unroll
         for (int m = 0; m < NP; ++m) dst[it.loff + ZItem<L>::S * m] = d2f(v[m]);
       }
+      if constexpr (BAR) __builtin_amdgcn_sched_barrier(0);
     });
   }
 };
@@ -147,8 +164,8 @@ template <int L, int SRC>
 __device__ __forceinline__ void z_item(const PatchDev* P, const WorkItem& wi, float* ws,
                                        const Physics& ph, double2* region, int lane) {
   const ZItem<L> it(P, wi, ws, lane);
-  ZSet<L, SRC, 0> s0;
-  ZSet<L, SRC, 1> s1;
+  ZSet<L, SRC, 0, false> s0;
+  ZSet<L, SRC, 1, false> s1;
   s0.load(it);
   s0.forward_update(it, ph, region);
   // at 8 points per lane the second set's loads are in flight during the
@@ -185,6 +202,41 @@ wave_z_fused_kernel(const PatchDev* __restrict__ patches, const WorkItem* __rest
   }
 }
 
+// One set of one item's lines per wavefront: wave w of the launch takes
+// item w / 2 and set w % 2 (the two sets of an item run on neighbouring
+// waves).  L has 8 points per lane (z_set_supported).
+template <int SRC, int L>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2)))
+wave_z_set_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items,
+                  int nitems, float* __restrict__ ws, Physics ph, int region_elems) {
+  static_assert(wfft::Line<L>::P == 8, "one set per wave is for 8 points per lane");
+  extern __shared__ double2 lds[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double2* region = lds + wave * region_elems;
+  const int nwork = 2 * nitems;
+  for (int w = blockIdx.x * kWavesPerBlock + wave; w < nwork; w += gridDim.x * kWavesPerBlock) {
+    const WorkItem wi = items[w >> 1];
+    const PatchDev* P = patches + wi.patch;
+    const ZItem<L> it(P, wi, ws, lane);
+    if ((w & 1) == 0) {
+      ZSet<L, SRC, 0, true> set;
+      set.load(it);
+      set.forward_update(it, ph, region);
+      set.inverse_store(it, region);
+    } else {
+      ZSet<L, SRC, 1, true> set;
+      set.load(it);
+      set.forward_update(it, ph, region);
+      set.inverse_store(it, region);
+    }
+  }
+}
+
+bool z_set_supported(int nz) {
+  return nz == 32 || nz == 64 || nz == 128 || nz == 256 || nz == 512;
+}
+
 bool z_supported(int nz) {
   return nz == 32 || nz == 48 || nz == 64 || nz == 96 || nz == 128 || nz == 192 || nz == 256 ||
          nz == 384 || nz == 512;
@@ -211,6 +263,39 @@ hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_set_len(int src, const LaunchShape& sh, hipStream_t stream,
+                          const PatchDev* patches, const WorkItem* items, int nitems, float* w,
+                          Physics ph, int region) {
+  switch (src) {
+    case kVacuum:
+      hipLaunchKernelGGL((wave_z_set_kernel<kVacuum, L>), dim3(sh.grid), dim3(kBlock), sh.lds_bytes,
+                         stream, patches, items, nitems, w, ph, region);
+      break;
+    case kPstdVacuum:
+      hipLaunchKernelGGL((wave_z_set_kernel<kPstdVacuum, L>), dim3(sh.grid), dim3(kBlock),
+                         sh.lds_bytes, stream, patches, items, nitems, w, ph, region);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_z_set(int src, int nz, const LaunchShape& sh, hipStream_t stream,
+                        const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
+                        Physics ph, int region) {
+  float* w = static_cast<float*>(ws);
+  switch (nz) {
+    case 32: return launch_set_len<32>(src, sh, stream, patches, items, nitems, w, ph, region);
+    case 64: return launch_set_len<64>(src, sh, stream, patches, items, nitems, w, ph, region);
+    case 128: return launch_set_len<128>(src, sh, stream, patches, items, nitems, w, ph, region);
+    case 256: return launch_set_len<256>(src, sh, stream, patches, items, nitems, w, ph, region);
+    case 512: return launch_set_len<512>(src, sh, stream, patches, items, nitems, w, ph, region);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t configure_attributes() {

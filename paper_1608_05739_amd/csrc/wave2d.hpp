@@ -26,6 +26,14 @@ hipError_t launch_z_fused(int src, const LaunchShape& sh, hipStream_t stream,
                           const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
                           Physics ph, int region);
 
+// The same pass with one polarization set per wavefront, for z lines of one
+// length nz in z_set_supported (8 points per lane): the launch runs 2 nitems
+// wavefronts, two per item; every item's patch must have this nz.
+bool z_set_supported(int nz);
+hipError_t launch_z_set(int src, int nz, const LaunchShape& sh, hipStream_t stream,
+                        const PatchDev* patches, const WorkItem* items, int nitems, void* ws,
+                        Physics ph, int region);
+
 hipError_t configure_attributes();
 
 // Fused z pass over 3D patches (wave3d.hip), PSATD forms (src kVacuum, kRho,

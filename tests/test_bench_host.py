@@ -100,6 +100,7 @@ def test_kernel_names_map_to_passes():
                                 "psatd::PatchDev const*)") == "x_r2c_fwd"
     assert bench.pass_of_kernel("void psatd::wave2d::wave_z_fused_kernel<0>(...)") == "z_fused"
     assert bench.pass_of_kernel("void psatd::wave2d::(anonymous namespace)::wave_z3_fused_kernel<1>(...)") == "z_fused"
+    assert bench.pass_of_kernel("void psatd::wave2d::wave_z_set_kernel<0, 256>(...)") == "z_fused"
     assert bench.pass_of_kernel("__amd_rocclr_copyBuffer") is None
 
 
