@@ -226,11 +226,12 @@ psatd_status psatd_push_scratch(psatd_plan_t plan, const psatd_fields* fields, i
 /* Like psatd_push, but records a HIP event pair around every pass on
  * `hip_stream`, synchronizes at the end and writes the mean duration of each
  * pass in milliseconds to ms_per_pass[0 .. npass-1] (npass from
- * psatd_pass_count).  Passes launched once per line length run those
- * launches one after the other, or, in a PSATD_FLAG_GRAPH plan, as the
- * parallel branches of its graph (so each pass is timed as the graph runs
- * it).  With sources, nsteps > 1 reuses the same J and rho in every step.
- * For measurement only. */
+ * psatd_pass_count).  A PSATD_FLAG_GRAPH plan launches each pass as a graph
+ * of its own, captured at plan time like the step's graph (a pass launched
+ * once per line length runs those launches as parallel branches), so each
+ * pass is timed as the step's graph runs it; other plans enqueue the
+ * kernels one after the other.  With sources, nsteps > 1 reuses the same J
+ * and rho in every step.  For measurement only. */
 psatd_status psatd_push_profiled(psatd_plan_t plan, const psatd_fields* fields,
                                  int32_t nsteps, void* hip_stream, double* ms_per_pass,
                                  int32_t max_pass);

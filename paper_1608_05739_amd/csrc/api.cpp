@@ -219,6 +219,10 @@ struct psatd_plan_s {
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
+  // one graph per pass (graph plans), for psatd_push_profiled to time each
+  // pass as the step's graph runs it
+  std::vector<hipGraphExec_t> pass_exec;
+  std::vector<hipGraph_t> pass_graphs;
   FieldPtrs* d_fieldtab = nullptr;  // field pointers the graph's kernels read (FieldPtrs::table)
   // graph capture: the launches of a pass with one launch per length run on
   // side streams forked from the capture stream and joined back, so that the
@@ -237,7 +241,17 @@ struct psatd_plan_s {
 
 namespace {
 
+void free_pass_graphs(psatd_plan_s* p) {
+  for (hipGraphExec_t x : p->pass_exec)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t g : p->pass_graphs)
+    if (g) (void)hipGraphDestroy(g);
+  p->pass_exec.clear();
+  p->pass_graphs.clear();
+}
+
 void free_plan_memory(psatd_plan_s* p) {
+  free_pass_graphs(p);
   for (hipEvent_t ev : p->fork_events) (void)hipEventDestroy(ev);
   for (hipStream_t st : p->side_streams) (void)hipStreamDestroy(st);
   p->fork_events.clear();
@@ -1183,6 +1197,7 @@ psatd_status build_graph(psatd_plan_s* plan) {
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   plan->graph_exec = nullptr;
   plan->graph = nullptr;
+  free_pass_graphs(plan);
   if (!plan->ws) return PSATD_OK;  // built when the workspace arrives
   hipError_t e = hipSuccess;
   if (!plan->d_fieldtab) {
@@ -1240,6 +1255,28 @@ psatd_status build_graph(psatd_plan_s* plan) {
     return hip_fail(e, "hipGraphInstantiate");
   }
   plan->graph = graph;
+  // each pass alone, captured the same way
+  for (size_t i = 0; i < plan->passes.size(); ++i) {
+    e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    cs = enqueue_pass(plan, plan->passes[i], fp, plan->capture_stream, plan->ws,
+                      forks[i].side ? &forks[i] : nullptr);
+    hipGraph_t pg = nullptr;
+    e = hipStreamEndCapture(plan->capture_stream, &pg);
+    if (cs != PSATD_OK) {
+      if (pg) (void)hipGraphDestroy(pg);
+      return cs;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t px = nullptr;
+    e = hipGraphInstantiate(&px, pg, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(pg);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    plan->pass_graphs.push_back(pg);
+    plan->pass_exec.push_back(px);
+  }
   return PSATD_OK;
 }
 
@@ -1911,14 +1948,24 @@ static psatd_status push_impl(psatd_plan_t plan, const psatd_fields* fields, int
     std::vector<hipEvent_t> ev(2 * np * nsteps);
     for (auto& x : ev)
       if (hipEventCreate(&x) != hipSuccess) return fail(PSATD_ERR_HIP, "hipEventCreate");
-    // a graph plan's per-length launches run as parallel branches, as in
-    // its graph, so each pass is timed as the graph runs it
-    const std::vector<Fork> forks = plan_forks(plan);
+    // a graph plan runs each pass's own graph (captured like the step's), so
+    // each pass is timed as the step's graph runs it
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    const bool graphs = (plan->cfg.flags & PSATD_FLAG_GRAPH) &&
+                        static_cast<int>(plan->pass_exec.size()) == np &&
+                        hipStreamIsCapturing(s, &cst) == hipSuccess && cst == hipStreamCaptureStatusNone;
     psatd_status rs = PSATD_OK;
+    if (graphs && launch_store_fields(fp, plan->d_fieldtab, s) != hipSuccess)
+      rs = fail(PSATD_ERR_HIP, "field table");
     for (int n = 0; n < nsteps && rs == PSATD_OK; ++n)
       for (int i = 0; i < np && rs == PSATD_OK; ++i) {
         (void)hipEventRecord(ev[2 * (n * np + i)], s);
-        rs = enqueue_pass(plan, plan->passes[i], fp, s, plan->ws, forks[i].side ? &forks[i] : nullptr);
+        if (graphs) {
+          const hipError_t ge = hipGraphLaunch(plan->pass_exec[i], s);
+          if (ge != hipSuccess) rs = hip_fail(ge, "hipGraphLaunch");
+        } else {
+          rs = enqueue_pass(plan, plan->passes[i], fp, s, plan->ws);
+        }
         (void)hipEventRecord(ev[2 * (n * np + i) + 1], s);
       }
     hipError_t e = hipStreamSynchronize(s);
