@@ -149,16 +149,18 @@ def ingest_traffic(fetch_csv, write_csv, workload_index, calib_mib):
         data = {}
     h = kernel_source_hash()
     # the plan's final kernels only (not the autotuner's trial launches)
-    fetch = [(n, v) for n, _, v in final_dispatches([r for r in fetch_all if pass_of_kernel(r[0])])]
-    write = [(n, v) for n, _, v in final_dispatches([r for r in write_all if pass_of_kernel(r[0])])]
-    passes = sorted({pass_of_kernel(n) for n, _ in fetch} - {None})
+    fetch = [((n, g), v) for n, g, v in final_dispatches([r for r in fetch_all if pass_of_kernel(r[0])])]
+    write = [((n, g), v) for n, g, v in final_dispatches([r for r in write_all if pass_of_kernel(r[0])])]
+    passes = sorted({pass_of_kernel(k[0]) for k, _ in fetch} - {None})
     for pname in passes:
-        # a pass launched per length: one kernel per length, each once a step
+        # a pass launched per length: one launch (kernel and grid: one kernel
+        # may serve several lengths at different grids) per length, each once
+        # a step
         f_kib = w_kib = 0.0
         ndisp = 0
-        for kname in sorted({n for n, _ in fetch if pass_of_kernel(n) == pname}):
-            fv = [v for n, v in fetch if n == kname]
-            wv = [v for n, v in write if n == kname]
+        for key in sorted({k for k, _ in fetch if pass_of_kernel(k[0]) == pname}):
+            fv = [v for k, v in fetch if k == key]
+            wv = [v for k, v in write if k == key]
             if not fv or not wv:
                 continue
             f_kib += sum(fv) / len(fv)

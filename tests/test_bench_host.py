@@ -72,6 +72,25 @@ def test_traffic_ingest_scales_by_the_calibration_copy(tmp_path, monkeypatch):
         pytest.approx((30.0 * 2.0 + 3.0) * 1024.0)
 
 
+def test_traffic_ingest_sums_one_kernel_launched_at_several_grids(tmp_path, monkeypatch):
+    # one kernel name serving several lengths (one launch per length, at its
+    # own grid) counts once per launch, not averaged over its launches
+    kib = 1024 * 1024.0
+    z = "wave2d::wave_z_fused_kernel<0>(...)"
+    zs = "wave2d::wave_z_set_kernel<0, 64>(...)"
+    steps = [(z, 10, 100.0), (z, 20, 300.0), (zs, 30, 50.0)] * 4
+    fetch = [("__amd_rocclr_copyBuffer", 1, kib / 2)] + steps
+    write = [("__amd_rocclr_copyBuffer", 1, kib)] + [(n, g, v / 10) for n, g, v in steps]
+    fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
+    _write_counters(fcsv, "FETCH_SIZE", fetch)
+    _write_counters(wcsv, "WRITE_SIZE", write)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    data = bench.ingest_traffic(str(fcsv), str(wcsv), 3, 1024)
+    e = data["2d-256patches-64to512-vacuum-500steps:z_fused"]
+    assert e["bytes_per_launch"] == pytest.approx((450.0 * 2.0 + 45.0) * 1024.0)
+    assert e["dispatches"] == 12
+
+
 def test_final_dispatches_skip_the_autotuner_trials():
     rows = [("a", 1), ("b", 4), ("a", 2), ("b", 4), ("c", 5),   # trials
             ("a", 2), ("b", 3), ("c", 8), ("a", 2), ("b", 3), ("c", 8)]
