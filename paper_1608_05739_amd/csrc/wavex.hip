@@ -66,6 +66,52 @@ __device__ __forceinline__ int partner(int k) {
   return k == 0 ? 0 : L - k;
 }
 
+// cos and sin of pi m / P (m < P) for the points per lane P = 8, 12, 16,
+// from first-octant constants, so that the symmetries hold exactly.
+constexpr double kC12 = 0.96592582628906828675;  // cos(pi/12)
+constexpr double kS12 = 0.25881904510252076235;  // sin(pi/12)
+constexpr double kCa = 0.98078528040323044913;   // cos(pi/16)
+constexpr double kSa = 0.19509032201612826785;   // sin(pi/16)
+constexpr double kCb = 0.83146961230254523708;   // cos(3 pi/16)
+constexpr double kSb = 0.55557023301960222474;   // sin(3 pi/16)
+template <int P>
+constexpr double cos_pm(int m) {
+  if constexpr (P == 8) {
+    constexpr double t[8] = {1.0, kC1, kR2, kS1, 0.0, -kS1, -kR2, -kC1};
+    return t[m];
+  } else if constexpr (P == 12) {
+    constexpr double t[12] = {1.0, kC12, kH3, kR2, 0.5, kS12, 0.0, -kS12, -0.5, -kR2, -kH3, -kC12};
+    return t[m];
+  } else {
+    static_assert(P == 16, "points per lane");
+    constexpr double t[16] = {1.0, kCa, kC1, kCb, kR2, kSb, kS1, kSa,
+                              0.0, -kSa, -kS1, -kSb, -kR2, -kCb, -kC1, -kCa};
+    return t[m];
+  }
+}
+template <int P>
+constexpr double sin_pm(int m) {
+  if constexpr (P == 8) {
+    constexpr double t[8] = {0.0, kS1, kR2, kC1, 1.0, kC1, kR2, kS1};
+    return t[m];
+  } else if constexpr (P == 12) {
+    constexpr double t[12] = {0.0, kS12, 0.5, kR2, kH3, kC12, 1.0, kC12, kH3, kR2, 0.5, kS12};
+    return t[m];
+  } else {
+    constexpr double t[16] = {0.0, kSa, kS1, kSb, kR2, kCb, kC1, kCa,
+                              1.0, kCa, kC1, kCb, kR2, kSb, kS1, kSa};
+    return t[m];
+  }
+}
+
+// The r2c post-twiddle W^k = exp(-i pi k / L) of the lane's point m
+// (k = s + S m): W^s, one read of the plan's table, times exp(-i pi m / P),
+// a constant (S P = L).
+template <int P>
+__device__ __forceinline__ double2 post_twiddle(double2 ws, int m) {
+  return m == 0 ? ws : cmul(ws, make_double2(cos_pm<P>(m), -sin_pm<P>(m)));
+}
+
 template <int L>
 __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
                            const FieldPtrs& fields, float* __restrict__ ws, double2* lds) {
@@ -99,6 +145,7 @@ __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
 #pragma unroll
   for (int m = 0; m < NP; ++m) line[wfft::pa(s + S * m)] = v[m];
   wfft::wave_sync();
+  const double2 wpost = gload(P->post, s);
   float2 out[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
@@ -111,7 +158,7 @@ __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
       const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
       const double2 d = make_double2(a.x - b.x, a.y + b.y);
       const double2 o = make_double2(0.5 * d.y, -0.5 * d.x);
-      out[m] = d2f(cadd(e, cmul(gload(P->post, k), o)));
+      out[m] = d2f(cadd(e, cmul(post_twiddle<NP>(wpost, m), o)));
     }
   }
   wfft::wave_sync();  // every partner read is done before the staging overwrites the region
@@ -175,6 +222,7 @@ __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
   tws.load(P->fx.tw, s);
   // c2r pre-step from the staged row (both k and L - k are there)
   const float2* const stg = reinterpret_cast<const float2*>(region) + g * XT::ROW;
+  const double2 wpost = gload(P->post, s);
   double2 v[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
@@ -186,7 +234,7 @@ __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
       const double2 b = f2d(stg[partner<L>(k)]);
       const double2 p = make_double2(a.x + b.x, a.y - b.y);
       const double2 d = make_double2(a.x - b.x, a.y + b.y);
-      const double2 t1 = cmul(cconj(gload(P->post, k)), d);
+      const double2 t1 = cmul(cconj(post_twiddle<NP>(wpost, m)), d);
       v[m] = make_double2(p.x - t1.y, p.y + t1.x);
     }
   }
