@@ -114,7 +114,8 @@ __device__ __forceinline__ double2 post_twiddle(double2 ws, int m) {
 
 template <int L>
 __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
-                           const FieldPtrs& fields, float* __restrict__ ws, double2* lds) {
+                           const FieldPtrs& fields, float* __restrict__ ws, double2* lds,
+                           const wfft::Twiddles<L>& tws) {
   using LN = wfft::Line<L>;
   using XT = XTile<L>;
   constexpr int NP = LN::P;
@@ -133,8 +134,6 @@ __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
   const float2* src = reinterpret_cast<const float2*>(
                           static_cast<const float*>(field_ptr(fields, wi.comp)) + P->off_real) +
                       static_cast<long long>(z) * L;
-  wfft::Twiddles<L> tws;
-  tws.load(P->fx.tw, s);
   double2 v[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) v[m] = f2d(src[s + S * m]);
@@ -187,7 +186,8 @@ __device__ void x_fwd_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
 
 template <int L>
 __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
-                           const FieldPtrs& fields, float* __restrict__ ws, double2* lds) {
+                           const FieldPtrs& fields, float* __restrict__ ws, double2* lds,
+                           const wfft::Twiddles<L>& tws) {
   using LN = wfft::Line<L>;
   using XT = XTile<L>;
   constexpr int NP = LN::P;
@@ -218,8 +218,6 @@ __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
   }
   __syncthreads();
 
-  wfft::Twiddles<L> tws;
-  tws.load(P->fx.tw, s);
   // c2r pre-step from the staged row (both k and L - k are there)
   const float2* const stg = reinterpret_cast<const float2*>(region) + g * XT::ROW;
   const double2 wpost = gload(P->post, s);
@@ -256,7 +254,7 @@ __device__ void x_inv_tile(const PatchDev* __restrict__ P, const WorkItem& wi,
 // into the [kx][y][z] block of the z passes; the inverse pass the reverse.
 template <int L, int SIGN>
 __device__ void y_tile(const PatchDev* __restrict__ P, const WorkItem& wi, float* __restrict__ ws,
-                       double2* lds) {
+                       double2* lds, const wfft::Twiddles<L>& tws) {
   using LN = wfft::Line<L>;
   using XT = XTile<L>;
   constexpr int NP = LN::P;
@@ -280,8 +278,6 @@ __device__ void y_tile(const PatchDev* __restrict__ P, const WorkItem& wi, float
   // [z][kx][y]: line (kx, z) at (z mx + kx) L;  [kx][y][z]: (kx, y, z) at (kx L + y) nz + z
   float2* const yline = blk_x + (static_cast<long long>(z) * P->mx + kx) * L;
   float2* const zrun = blk_z + static_cast<long long>(kx) * L * nz + z0;
-  wfft::Twiddles<L> tws;
-  tws.load(P->fy.tw, s);
   constexpr int total = XT::T * L;
   double2 v[NP];
   if constexpr (SIGN < 0) {
@@ -332,14 +328,31 @@ __global__ void __launch_bounds__(512)
 wave_x_kernel(const PatchDev* __restrict__ patches, const WorkItem* __restrict__ items, int nitems,
               FieldPtrs fields, float* __restrict__ ws) {
   extern __shared__ double2 lds[];
+  if (static_cast<int>(blockIdx.x) >= nitems) return;
+  // The twiddle bases depend only on the length and the lane's position, and
+  // every item of this launch has length L.  The forward passes up to 512
+  // points keep one set for the whole launch (measured faster); the others
+  // request them per tile (holding them cost the inverse passes time, and the
+  // 1024-point kernels a wave per SIMD).
+  constexpr bool kHold = (KIND == kXFwd || KIND == kYFwd) && L <= 512;
+  const int s = (threadIdx.x & 63) % wfft::Line<L>::S;
+  wfft::Twiddles<L> tws;
+  if constexpr (kHold) {
+    const PatchDev* P0 = patches + items[0].patch;
+    tws.load(KIND == kYFwd ? P0->fy.tw : P0->fx.tw, s);
+  }
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const WorkItem wi = items[xcd_local_order(it, nitems)];
+    if constexpr (!kHold) {
+      const PatchDev* Pi = patches + wi.patch;
+      tws.load(KIND == kYFwd || KIND == kYInv ? Pi->fy.tw : Pi->fx.tw, s);
+    }
     if constexpr (KIND == kXFwd) {
-      x_fwd_tile<L>(patches + wi.patch, wi, fields, ws, lds);
+      x_fwd_tile<L>(patches + wi.patch, wi, fields, ws, lds, tws);
     } else if constexpr (KIND == kXInv) {
-      x_inv_tile<L>(patches + wi.patch, wi, fields, ws, lds);
+      x_inv_tile<L>(patches + wi.patch, wi, fields, ws, lds, tws);
     } else {
-      y_tile<L, KIND == kYFwd ? -1 : 1>(patches + wi.patch, wi, ws, lds);
+      y_tile<L, KIND == kYFwd ? -1 : 1>(patches + wi.patch, wi, ws, lds, tws);
     }
   }
 }
