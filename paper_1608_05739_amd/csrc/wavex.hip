@@ -104,6 +104,22 @@ constexpr double sin_pm(int m) {
   }
 }
 
+// Every entry lies on the unit circle, and the angle doubles where the
+// tables overlap (pi m / 8 = pi 2m / 16, pi m / 6 = pi 2m / 12).
+template <int P>
+constexpr bool half_turn_tables_ok() {
+  for (int m = 0; m < P; ++m) {
+    const double r = cos_pm<P>(m) * cos_pm<P>(m) + sin_pm<P>(m) * sin_pm<P>(m) - 1.0;
+    if (r > 4e-16 || r < -4e-16) return false;
+  }
+  return true;
+}
+static_assert(half_turn_tables_ok<8>() && half_turn_tables_ok<12>() && half_turn_tables_ok<16>(),
+              "cos / sin of pi m / P");
+static_assert(cos_pm<8>(3) == cos_pm<16>(6) && sin_pm<8>(5) == sin_pm<16>(10) &&
+                  cos_pm<12>(4) == 0.5 && sin_pm<12>(2) == 0.5,
+              "cos / sin of pi m / P");
+
 // The r2c post-twiddle W^k = exp(-i pi k / L) of the lane's point m
 // (k = s + S m): W^s, one read of the plan's table, times exp(-i pi m / P),
 // a constant (S P = L).
